@@ -1,0 +1,68 @@
+"""FP64 materialization of functional operands.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Definition "Functional Batched Einstein Summation" replaces each argument A by a
+function M(A): dom(A) -> codomain(A).  The oracle evaluates every such function
+on its whole domain first (materializes it) and then runs the plain loop nest,
+which is exactly what the definition's formula states.  The functions below are
+the operand kinds the library accepts; each is written from its mathematical
+definition in numpy.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+UNARY_OPS = ("id", "sin", "cos", "square")
+
+
+def strided_view(flat_source, shape, strides, offset=0) -> np.ndarray:
+    """M(A)[i_1..i_d] = S[offset + sum_k i_k * strides[k]] (element strides)."""
+    src = np.asarray(flat_source, dtype=np.float64).reshape(-1)
+    if len(shape) == 0:
+        return np.array(src[offset])
+    grids = np.indices(tuple(shape), dtype=np.int64)
+    pos = np.full(tuple(shape), offset, dtype=np.int64)
+    for k, s in enumerate(strides):
+        pos = pos + grids[k] * int(s)
+    return src[pos]
+
+
+def unary(x, op: str) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    if op == "id":
+        return x
+    if op == "sin":
+        return np.sin(x)
+    if op == "cos":
+        return np.cos(x)
+    if op == "square":
+        return x * x
+    raise ValueError(op)
+
+
+def elementwise(src0, op: str = "id", alpha: float = 1.0, beta: float = 0.0,
+                src1=None) -> np.ndarray:
+    """M(A)[idx] = alpha * op(S0[idx]) + beta (+ S1[idx] when given).
+
+    Covers the affine operands (alpha*A + beta) of the TCCG experiment, the
+    substitution rules u = P*P, v = 3 cos(Q) + 5, w = sin(R) of the functional
+    retrieval listing, and u = sin(a) + b.
+    """
+    val = float(alpha) * unary(src0, op) + float(beta)
+    if src1 is not None:
+        val = val + np.asarray(src1, dtype=np.float64)
+    return val
+
+
+def tet_jacobian(V) -> np.ndarray:
+    """Affine tetrahedron map x(xi) = v_0 + sum_r xi_r (v_{r+1} - v_0):
+    J[e, x, r] = d x_x / d xi_r = V[e, r+1, x] - V[e, 0, x], V of shape [e,4,3]."""
+    V = np.asarray(V, dtype=np.float64)
+    if V.ndim != 3 or V.shape[1:] != (4, 3):
+        raise ValueError("V must have shape [e, 4, 3]")
+    J = np.empty((V.shape[0], 3, 3), dtype=np.float64)
+    for x in range(3):
+        for r in range(3):
+            J[:, x, r] = V[:, r + 1, x] - V[:, 0, x]
+    return J

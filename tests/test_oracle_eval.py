@@ -1,0 +1,166 @@
+"""Pins of the oracle's loop-nest evaluator and gradient (CPU only).
+
+Each check ties the oracle to something other than itself: numpy's einsum or
+matmul (library routines for special cases), the paper's worked examples,
+closed forms (the GEMM gradient) and central finite differences.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import functional as F
+
+RNG = np.random.default_rng(12220)
+
+
+def _rand(*shape):
+    return RNG.standard_normal(shape)
+
+
+@pytest.mark.parametrize("notation,shapes", [
+    ("ij,ej->ei", [(10, 10), (64, 10)]),
+    ("er,rij,ej->ei", [(7, 3), (3, 5, 5), (7, 5)]),
+    ("rij,exr,ej->exi", [(3, 4, 4), (6, 3, 3), (6, 4)]),
+    ("abij,cdab->cdij", [(3, 2, 4, 2), (2, 3, 3, 2)]),
+    ("ijk,ik,ij,ij->i", [(5, 4, 3), (5, 3), (5, 4), (5, 4)]),
+    ("ij,ij->", [(4, 5), (4, 5)]),
+    ("ii->i", [(6, 6)]),
+    ("iij,j->i", [(3, 3, 4), (4,)]),
+    ("ab,bc,cd,de->ae", [(2, 3), (3, 4), (4, 2), (2, 3)]),
+    ("i,j->ij", [(4,), (5,)]),
+    ("xre,rij,xej->ei", [(3, 3, 5), (3, 4, 4), (3, 5, 4)]),
+])
+def test_matches_numpy_einsum(notation, shapes):
+    ops = [_rand(*s) for s in shapes]
+    got = oracle.einsum(notation, *ops)
+    ref = np.einsum(notation, *ops)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_zero_extent_gives_zero_fill():
+    # Shape allows 0 and an empty sum is 0 (Definition of a multidimensional
+    # array; Eq. (1)).
+    A = np.zeros((3, 0))
+    B = np.zeros((0, 4))
+    got = oracle.einsum("ik,kj->ij", A, B)
+    assert got.shape == (3, 4) and np.all(got == 0.0)
+
+
+def test_invalid_notations_rejected():
+    with pytest.raises(ValueError):
+        oracle.einsum("ij,jk->ii", _rand(2, 3), _rand(3, 2))   # repeated output index
+    with pytest.raises(ValueError):
+        oracle.einsum("ij->ik", _rand(2, 3))                   # output index not in inputs
+    with pytest.raises(ValueError):
+        oracle.einsum("ij,jk->ik", _rand(2, 3), _rand(4, 2))   # inconsistent extent
+
+
+def test_config1_is_a_gemm():
+    # R_b[e,i] = sum_j D_b[i,j] u[e,j] = (u @ D_b^T)[e,i]
+    u = _rand(64, 10)
+    for _ in range(3):
+        D = RNG.uniform(-1, 1, (10, 10))
+        np.testing.assert_allclose(oracle.einsum("ij,ej->ei", D, u), u @ D.T,
+                                   rtol=1e-13, atol=1e-13)
+
+
+def test_dense_pair_is_a_gemm_after_reshape():
+    # 'abij,cdab->cdij' is C[(cd),(ij)] = V[(cd),(ab)] @ T[(ab),(ij)]
+    a, i = 3, 2
+    T = _rand(a, a, i, i)
+    V = _rand(a, a, a, a)
+    got = oracle.einsum("abij,cdab->cdij", T, V)
+    ref = (V.reshape(a * a, a * a) @ T.reshape(a * a, i * i)).reshape(a, a, i, i)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_batched_example(paper_examples):
+    # Example 'Batched einsum': R1 = A B C, R2 = B C D (10 x 10 each).
+    ex = paper_examples["batched_example"]
+    arrs = {k: _rand(*s) for k, s in ex["shapes"].items()}
+    R = oracle.batched_einsum(ex["notation"], ex["table"], arrs)
+    np.testing.assert_allclose(R[0], arrs["A"] @ arrs["B"] @ arrs["C"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(R[1], arrs["B"] @ arrs["C"] @ arrs["D"], rtol=1e-12, atol=1e-12)
+
+
+def test_functional_retrieval_listing(paper_examples):
+    # Listing 'Computational scientist's view': u = P*P, v = 3 cos(Q) + 5,
+    # w = sin(R); y1[i0] = sum_i1 u v, y2[i0] = sum_i1 u w, i0 < 96, i1 < 4.
+    ex = paper_examples["functional_retrieval"]
+    n0, n1 = ex["domain"]["i0"], ex["domain"]["i1"]
+    P, Q, R = _rand(n0, n1), _rand(n1), _rand(n1)
+    U = F.elementwise(P, "square")
+    Vq = F.elementwise(Q, "cos", 3.0, 5.0)
+    Wr = F.elementwise(R, "sin")
+    y = oracle.batched_einsum("ij,j->i", [["U", "V"], ["U", "W"]],
+                              {"U": U, "V": Vq, "W": Wr})
+    # the generated OpenCL listing written out with numpy
+    p = P * P
+    y1 = (p * (3 * np.cos(Q) + 5)).sum(axis=1)
+    y2 = (p * np.sin(R)).sum(axis=1)
+    np.testing.assert_allclose(y[0], y1, rtol=1e-13)
+    np.testing.assert_allclose(y[1], y2, rtol=1e-13)
+
+
+def test_tet_jacobian_maps_reference_vertices():
+    # The affine map sends reference vertex 0 to v0 and unit vector r to
+    # v_{r+1}: x(e_r) - x(0) = J e_r = v_{r+1} - v_0.
+    V = RNG.uniform(0, 1, (5, 4, 3))
+    J = F.tet_jacobian(V)
+    for r in range(3):
+        xi = np.zeros(3)
+        xi[r] = 1.0
+        np.testing.assert_allclose(J @ xi, V[:, r + 1, :] - V[:, 0, :], rtol=0, atol=0)
+    # volume of the tetrahedron = |det J| / 6 (a closed form for the unit
+    # reference simplex)
+    e0 = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    np.testing.assert_allclose(np.linalg.det(F.tet_jacobian(e0[None]))[0], 1.0)
+
+
+def test_strided_view_matches_numpy_view():
+    W = _rand(3, 4, 5, 6)
+    got = F.strided_view(W, (5, 6, 3, 4), (6, 1, 120, 30), 0)
+    np.testing.assert_array_equal(got, W.transpose(2, 3, 0, 1))
+    J = _rand(7, 3, 3)
+    for x in range(3):
+        np.testing.assert_array_equal(F.strided_view(J, (7, 3), (9, 1), 3 * x), J[:, x, :])
+
+
+def test_einsum_at_matches_full():
+    A, B = _rand(6, 5), _rand(5, 7)
+    full = oracle.einsum("ik,kj->ij", A, B)
+    pos = np.array([0, 3, 17, 41])
+    np.testing.assert_allclose(oracle.einsum_at("ik,kj->ij", [A, B], pos), full.ravel()[pos],
+                               rtol=0, atol=0)
+
+
+def test_grad_closed_form_gemm():
+    # R = A B, <G, R> has dA = G B^T and dB = A^T G.
+    A, B, G = _rand(4, 3), _rand(3, 5), _rand(4, 5)
+    np.testing.assert_allclose(oracle.einsum_grad("ik,kj->ij", [A, B], G, 0), G @ B.T, rtol=1e-13)
+    np.testing.assert_allclose(oracle.einsum_grad("ik,kj->ij", [A, B], G, 1), A.T @ G, rtol=1e-13)
+
+
+@pytest.mark.parametrize("notation,shapes", [
+    ("abij,cdab->cdij", [(2, 2, 3, 2), (2, 3, 2, 2)]),
+    ("rij,exr,ej->exi", [(2, 3, 3), (2, 2, 2), (2, 3)]),
+    ("ii,i->i", [(3, 3), (3,)]),
+    ("ij,ij->", [(3, 4), (3, 4)]),
+])
+def test_grad_central_differences(notation, shapes):
+    ops = [_rand(*s) for s in shapes]
+    R = oracle.einsum(notation, *ops)
+    G = _rand(*R.shape) if R.ndim else np.array(RNG.standard_normal())
+    h = 1e-6
+    for k in range(len(ops)):
+        g = oracle.einsum_grad(notation, ops, G, k)
+        fd = np.zeros_like(ops[k])
+        # repeated labels read only the diagonal, so only those entries move
+        for idx in np.ndindex(ops[k].shape):
+            p = [o.copy() for o in ops]
+            m = [o.copy() for o in ops]
+            p[k][idx] += h
+            m[k][idx] -= h
+            fd[idx] = (np.sum(G * oracle.einsum(notation, *p)) -
+                       np.sum(G * oracle.einsum(notation, *m))) / (2 * h)
+        np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-7)
