@@ -1,0 +1,246 @@
+/*
+ * bes.h -- C ABI of the batched-einsum library (gfx950 / MI355X).
+ *
+ * A batched einsum is b einsums that share one Einstein notation and possibly
+ * some operands (Definition "Batched Einstein Summation"; arxiv 2601.12220).
+ * Operands may be functional: each argument is a function of its index tuple
+ * evaluated from one or two source buffers (Definition "Functional Batched
+ * Einstein Summation").  The library
+ *
+ *   1. parses and validates the notation and the b x n argument table,
+ *   2. maps the batched einsum to its colored induced graph (Appendix B.1),
+ *   3. labels that graph canonically (Algorithm "CanonicalizeBatchedEinsum"),
+ *   4. rebuilds the canonical batched einsum from the labeled graph (Appendix
+ *      B.2) together with the substitution maps back to the caller's names,
+ *   5. looks up a tuning record by (canonical key, GPU arch),
+ *   6. binds the caller's buffers to the canonical operand slots, and
+ *   7. launches hand-written HIP kernels on the caller's stream.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an int status (enum bes_status): 0 success,
+ *     > 0 success with a warning, < 0 error.  Nothing throws across the ABI.
+ *     On error, bes_last_error() returns a thread-local message.
+ *   - Device pointers are plain HIP device addresses; `hip_stream` is a
+ *     hipStream_t (NULL = the default stream).  The caller owns every device
+ *     buffer and every stream; the library keeps raw device pointers only for
+ *     the duration of a launch (a bes_batch keeps its own descriptor table).
+ *   - All shapes and strides are in elements, not bytes.
+ *   - Index names are the letters 'a'..'z' (grammar of the Listing "Grammar
+ *     for an index"), so a batched einsum has at most 26 distinct indices.
+ */
+#ifndef BES_H
+#define BES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum bes_status {
+  BES_OK = 0,
+  BES_W_NOTFOUND = 1,     /* no tuning record: the template default is used */
+  BES_E_INVALID = -1,     /* malformed notation or table, violated soundness
+                             condition of Eq. (1), repeated output index */
+  BES_E_UNSUPPORTED = -2, /* dtype the kernels lack, 0-dim operand, kind or
+                             size outside the library's limits */
+  BES_E_HIP = -3,         /* a HIP runtime call failed */
+  BES_E_NOMEM = -4,       /* host or device allocation failed */
+  BES_E_BUFFER = -5,      /* caller buffer too small; *len holds the need */
+  BES_E_STATE = -6        /* call not valid for this object (e.g. no GPU) */
+};
+
+/* Dtype codes are the DtypeRank values of the induced-graph construction
+ * (Appendix B.1, dtype ranks).  Canonicalization accepts all eight; the GPU
+ * kernels evaluate float32 and float64 only. */
+enum bes_dtype {
+  BES_INT8 = 1, BES_INT32 = 2, BES_INT64 = 3, BES_FLOAT16 = 4,
+  BES_FLOAT32 = 5, BES_FLOAT64 = 6, BES_COMPLEX64 = 7, BES_COMPLEX128 = 8
+};
+
+/* Operand kinds: the functions M(A) of a functional batched einsum that the
+ * kernels evaluate in registers (never materialized in device memory). */
+enum bes_kind {
+  BES_ARRAY = 0,        /* M(A)[idx] = S0[idx], S0 dense row-major, or
+                           strided if src_strides[0] is non-zero */
+  BES_VIEW = 1,         /* M(A)[idx] = S0[src_offset[0] + sum idx_k*stride_k] */
+  BES_ELEMENTWISE = 2,  /* M(A)[idx] = alpha*op(S0[idx]) + beta (+ S1[idx]
+                           when nsrc == 2) */
+  BES_TET_JACOBIAN = 3  /* M(A)[e,x,r] = S0[e,r+1,x] - S0[e,0,x]: Jacobian of
+                           the affine map of a tetrahedron whose 4 vertex
+                           coordinates are S0[e,4,3]; the operand is 3-d with
+                           extents (e,3,3); src_strides[0] are S0's strides */
+};
+
+enum bes_unary { BES_OP_ID = 0, BES_OP_SIN = 1, BES_OP_COS = 2, BES_OP_SQUARE = 3 };
+
+#define BES_MAX_DIM 8
+#define BES_MAX_SRC 2
+#define BES_MAX_B 64
+#define BES_MAX_N 8
+
+/* Descriptor of one argument of the batched einsum.
+ *   kind, dtype, ndim, shape: as above; ndim in 1..BES_MAX_DIM.
+ *   nsrc: number of source buffers (1, or 2 for ELEMENTWISE with S1).
+ *   src_offset[s], src_strides[s][d]: element offset and strides of source s
+ *     (all-zero strides mean dense row-major in `shape`; for TET_JACOBIAN the
+ *     three strides address S0[e, vertex, coordinate]).
+ *   op, alpha, beta: the ELEMENTWISE function. */
+typedef struct bes_operand {
+  int32_t kind;
+  int32_t dtype;
+  int32_t ndim;
+  int32_t nsrc;
+  int64_t shape[BES_MAX_DIM];
+  int64_t src_offset[BES_MAX_SRC];
+  int64_t src_strides[BES_MAX_SRC][BES_MAX_DIM];
+  int32_t op;
+  int32_t reserved;
+  double alpha;
+  double beta;
+} bes_operand;
+
+/* Kernel templates and their tunable parameters (the "transformations" whose
+ * performance facts the tuning database stores, Section "Integration ..."). */
+enum bes_template {
+  BES_T_AUTO = 0,        /* let the planner pick */
+  BES_T_FEM_STREAM = 1,  /* per-element operands streamed from HBM, small
+                            shared operand uniform per wave; p[0] = elements
+                            per block (64..512), p[1] = blocks per CU */
+  BES_T_GENERIC = 2,     /* any batched einsum; p[0] = outputs per tile,
+                            p[1] = lanes per output (1,2,4,...,64) */
+  BES_T_MFMA = 3         /* dense contraction on MFMA (FP32 in, FP32 acc);
+                            p[0] = tile M, p[1] = tile N, p[2] = split */
+};
+
+typedef struct bes_config {
+  int32_t template_id;
+  int32_t p[6];
+} bes_config;
+
+typedef struct bes_ctx bes_ctx;
+typedef struct bes_plan bes_plan;
+typedef struct bes_batch bes_batch;
+
+/* Context: owns the tuning database (DS9).  `tuning_db_path` may be NULL
+ * (no database).  A missing file is created on the first record; malformed
+ * lines are skipped with a warning on stderr when BES_LOG >= 1.
+ * Makes no HIP call. */
+int bes_ctx_create(bes_ctx **out, const char *tuning_db_path);
+void bes_ctx_destroy(bes_ctx *ctx);
+
+/* Register a batched einsum (steps 1-6 above; host only, no HIP call).
+ *   notation: "in_1,...,in_n->out", letters a..z (repeated letters inside one
+ *     input address a diagonal; output letters must be distinct and appear in
+ *     some input -- the soundness conditions after Eq. (1)).
+ *   b, n: batch size (1..BES_MAX_B) and operands per einsum (1..BES_MAX_N).
+ *   args[n_args]: argument descriptors; every argument must occur in `table`.
+ *   table[b*n]: row-major argument ids; row i lists the operands of member i.
+ * Every index must have one extent across the whole batch.  All arguments
+ * share one dtype (the output dtype).  On success *out owns a plan; destroy it
+ * with bes_plan_destroy.  The returned status is BES_W_NOTFOUND when the
+ * context has no record for the plan's key on `gfx950`. */
+int bes_register(bes_ctx *ctx, const char *notation, int32_t b, int32_t n,
+                 int32_t n_args, const bes_operand *args, const int32_t *table,
+                 bes_plan **out);
+void bes_plan_destroy(bes_plan *plan);
+
+/* Canonical key (the tuning-database identity): the canonical batched einsum
+ * with its extents and dtypes, identical for every isomorphic registration
+ * (Definition "Canonicalization of a batched einsum").  Written with a NUL
+ * into buf[cap]; *len receives the length without the NUL.  buf may be NULL
+ * to query the length (returns BES_E_BUFFER when cap is too small). */
+int bes_plan_key(const bes_plan *plan, char *buf, size_t cap, size_t *len);
+
+/* The canonical batched einsum in the paper's tuple notation, e.g.
+ * "(1, 2, (a), ((a b), (a c)), ((A_0, A_1)))"; same buffer convention. */
+int bes_plan_canonical(const bes_plan *plan, char *buf, size_t cap, size_t *len);
+
+/* Substitution maps from the canonical form to the registration
+ * (Algorithm "CanonicalizeBatchedEinsum" returns sigma^A and sigma^I; the
+ * library also returns sigma^i and sigma^j):
+ *   member_map[k] = user member of canonical member k        (b entries)
+ *   pos_map[j]    = user operand position of canonical pos j (n entries)
+ *   arg_map[a]    = user argument id of canonical arg A_a    (n_args entries)
+ *   index_map[c]  = user letter of canonical index 'a'+c     (n_index chars)
+ * Any pointer may be NULL.  *n_index (optional) gets the number of indices. */
+int bes_plan_maps(const bes_plan *plan, int32_t *member_map, int32_t *pos_map,
+                  int32_t *arg_map, char *index_map, int32_t *n_index);
+
+/* Induced graph of the registration (Appendix B.1) and of the canonical form:
+ * n_nodes, then optionally the row-major adjacency (n_nodes^2 bytes, 0/1) and
+ * the colors (1..9).  which = 0: induced graph in construction order;
+ * which = 1: canonically relabeled graph. */
+int bes_plan_graph(const bes_plan *plan, int32_t which, int32_t *n_nodes,
+                   uint8_t *adj, int32_t *colors);
+
+/* Check compliance conditions C1-C30 of Appendix B.2 on a colored digraph.
+ * Returns 0 if compliant, else the number (1..30) of the first violated
+ * condition.  adj is n*n row-major bytes, colors n entries. */
+int bes_check_compliance(int32_t n, const uint8_t *adj, const int32_t *colors);
+
+/* Canonical labeling of a vertex-colored digraph (the GetCanonLabel step):
+ * label[v] = canonical position of vertex v.  Labels are invariant: two
+ * isomorphic colored digraphs relabel to the same adjacency. */
+int bes_canonical_labeling(int32_t n, const uint8_t *adj, const int32_t *colors,
+                           int32_t *label);
+
+/* Tuning: look up (key, arch) and install the record's config in the plan.
+ * Returns BES_OK on a hit, BES_W_NOTFOUND (and installs the template default)
+ * on a miss. */
+int bes_plan_lookup(bes_ctx *ctx, bes_plan *plan, const char *arch);
+int bes_plan_get_config(const bes_plan *plan, bes_config *cfg);
+/* Install a config (autotuner); BES_E_UNSUPPORTED if the template cannot
+ * evaluate this plan. */
+int bes_plan_set_config(bes_plan *plan, const bes_config *cfg);
+/* Append a performance fact; the last record for (key, arch) wins. */
+int bes_db_record(bes_ctx *ctx, const char *key, const char *arch,
+                  const bes_config *cfg, double seconds);
+/* Number of lookups that hit / missed since the context was created. */
+int bes_ctx_stats(const bes_ctx *ctx, int64_t *hits, int64_t *misses);
+
+/* Launch one plan on `hip_stream`.
+ *   src_ptrs: device pointers of every argument's sources, flattened in user
+ *     argument order then source order (sum over args of nsrc entries).
+ *   out_ptrs: b device pointers of the outputs in user member order; output i
+ *     is dense row-major with the extents of the output indices in the
+ *     notation's order and is overwritten.
+ * Asynchronous; returns BES_E_HIP if the launch could not be enqueued. */
+int bes_launch(const bes_plan *plan, const void *const *src_ptrs,
+               void *const *out_ptrs, void *hip_stream);
+
+/* Persistent batched launch of many plans (one kernel over a device work list
+ * of (plan, member, tile) items, captured once in a hipGraph).
+ * bes_batch_create uploads the descriptor table of every plan's current
+ * config; bes_batch_launch binds pointers (src_ptrs[p], out_ptrs[p] as in
+ * bes_launch for plan p) and replays.  Pointers may change between launches.
+ * Set BES_NO_GRAPH=1 to launch without graph capture. */
+int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count,
+                     bes_batch **out);
+int bes_batch_launch(bes_batch *batch, const void *const *const *src_ptrs,
+                     void *const *const *out_ptrs, void *hip_stream);
+void bes_batch_destroy(bes_batch *batch);
+
+/* Adjoint: the batched einsum giving d<G, R>/dA for the arguments at operand
+ * position `pos` of a forward plan.  Its operands are, per forward member i,
+ * (G_i, the other operands of member i) and its output index list is the
+ * forward index list of position `pos`.  Members whose position-`pos`
+ * argument is the same are summed into one output.  The adjoint plan is
+ * itself registered (canonicalized, keyed, tuned).
+ *   Launch it with src_ptrs = [the b gradients G_i (dense, forward output
+ *   shape), then the forward plan's src_ptrs] and out_ptrs = one pointer per
+ *   distinct position-`pos` argument, in order of first occurrence down the
+ *   rows (n_out receives that count).  Outputs are dense in the argument's
+ *   shape; for a VIEW argument the gradient of the view is written dense.
+ * BES_E_UNSUPPORTED if the position has a repeated index or a functional
+ * argument that is not an ARRAY/VIEW. */
+int bes_adjoint(bes_ctx *ctx, const bes_plan *fwd, int32_t pos,
+                bes_plan **out, int32_t *n_out);
+
+const char *bes_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BES_H */

@@ -1,0 +1,497 @@
+// C ABI of the batched-einsum library (declared in include/bes.h).
+//
+// Registration, canonicalization, tuning lookup and binding are host-only and
+// make no HIP call, so they run on machines without a GPU.  Launch entry
+// points enqueue hand-written HIP kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bes.h"
+#include "host/canon.h"
+#include "host/db.h"
+#include "host/graph.h"
+#include "host/plan.h"
+#include "host/spec.h"
+#include "kernels/kernels.h"
+
+struct bes_ctx {
+  bes::TuningDB db;
+};
+
+struct bes_plan {
+  bes::Plan p;
+};
+
+struct bes_batch {
+  std::vector<const bes::Plan *> plans;
+  bool f64 = false;
+  int n_items = 0;
+  int grid = 0;
+  int device = -1;
+  GenEinsum *d_table = nullptr;
+  GenPtrs *d_ptrs = nullptr;
+  GenItem *d_items = nullptr;
+  unsigned *d_counters = nullptr;
+  GenPtrs *h_ptrs = nullptr;  // pinned staging for pointer updates
+  std::vector<GenPtrs> last;
+  bool have_last = false;
+  hipEvent_t staged = nullptr;
+  hipStream_t capture_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = true;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int copy_out(const std::string &s, char *buf, size_t cap, size_t *len) {
+  if (len) *len = s.size();
+  if (!buf) return cap == 0 ? BES_OK : fail(BES_E_INVALID, "NULL buffer with non-zero capacity");
+  if (cap < s.size() + 1) return fail(BES_E_BUFFER, "buffer too small");
+  std::memcpy(buf, s.c_str(), s.size() + 1);
+  return BES_OK;
+}
+
+const char *kDefaultArch = "gfx950";
+
+int apply_lookup(bes_ctx *ctx, bes::Plan &p, const std::string &arch) {
+  p.cfg = bes::default_config(p);
+  p.cfg_from_db = false;
+  if (!ctx) return BES_W_NOTFOUND;
+  const bes::TuningRecord *r = ctx->db.find(p.key, arch);
+  if (r && bes::template_supported(p, r->cfg.template_id)) {
+    p.cfg = r->cfg;
+    p.cfg_from_db = true;
+    ++ctx->db.hits;
+    return BES_OK;
+  }
+  ++ctx->db.misses;
+  return BES_W_NOTFOUND;
+}
+
+bool env_flag(const char *name) {
+  const char *s = std::getenv(name);
+  return s && *s && std::strcmp(s, "0") != 0;
+}
+
+hipError_t ensure_generic_dev(const bes::Plan &p, const GenEinsum &g) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  bool same_cfg = std::memcmp(&p.gen_dev_cfg, &p.cfg, sizeof p.cfg) == 0;
+  if (p.gen_dev && p.gen_dev_device == dev && same_cfg) return hipSuccess;
+  if (p.gen_dev && p.gen_dev_device != dev) {
+    (void)hipFree(p.gen_dev);
+    p.gen_dev = nullptr;
+  }
+  if (!p.gen_dev) {
+    e = hipMalloc(&p.gen_dev, sizeof(GenEinsum));
+    if (e != hipSuccess) {
+      p.gen_dev = nullptr;
+      return e;
+    }
+  }
+  e = hipMemcpy(p.gen_dev, &g, sizeof g, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  p.gen_dev_device = dev;
+  p.gen_dev_cfg = p.cfg;
+  return hipSuccess;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(BES_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bes_last_error(void) { return g_err.c_str(); }
+
+int bes_ctx_create(bes_ctx **out, const char *tuning_db_path) {
+  if (!out) return fail(BES_E_INVALID, "out is NULL");
+  *out = nullptr;
+  bes_ctx *c = new (std::nothrow) bes_ctx;
+  if (!c) return fail(BES_E_NOMEM, "out of host memory");
+  std::string err;
+  int rc = c->db.open(tuning_db_path, err);
+  if (rc) {
+    delete c;
+    return fail(rc, err);
+  }
+  *out = c;
+  return BES_OK;
+}
+
+void bes_ctx_destroy(bes_ctx *ctx) { delete ctx; }
+
+int bes_register(bes_ctx *ctx, const char *notation, int32_t b, int32_t n, int32_t n_args,
+                 const bes_operand *args, const int32_t *table, bes_plan **out) {
+  if (!out) return fail(BES_E_INVALID, "out is NULL");
+  *out = nullptr;
+  try {
+    bes_plan *P = new bes_plan;
+    std::string err;
+    int rc = bes::make_spec(notation, b, n, n_args, args, table, P->p.spec, err);
+    if (rc == BES_OK) rc = bes::build_plan(P->p, err);
+    if (rc != BES_OK) {
+      delete P;
+      return fail(rc, err);
+    }
+    rc = apply_lookup(ctx, P->p, kDefaultArch);
+    *out = P;
+    return rc;
+  } catch (const std::bad_alloc &) {
+    return fail(BES_E_NOMEM, "out of host memory");
+  }
+}
+
+void bes_plan_destroy(bes_plan *plan) {
+  if (!plan) return;
+  if (plan->p.gen_dev) (void)hipFree(plan->p.gen_dev);
+  delete plan;
+}
+
+int bes_plan_key(const bes_plan *plan, char *buf, size_t cap, size_t *len) {
+  if (!plan) return fail(BES_E_INVALID, "plan is NULL");
+  return copy_out(plan->p.key, buf, cap, len);
+}
+
+int bes_plan_canonical(const bes_plan *plan, char *buf, size_t cap, size_t *len) {
+  if (!plan) return fail(BES_E_INVALID, "plan is NULL");
+  return copy_out(plan->p.tuple, buf, cap, len);
+}
+
+int bes_plan_maps(const bes_plan *plan, int32_t *member_map, int32_t *pos_map, int32_t *arg_map,
+                  char *index_map, int32_t *n_index) {
+  if (!plan) return fail(BES_E_INVALID, "plan is NULL");
+  const bes::Canonical &c = plan->p.canon;
+  if (member_map) std::copy(c.member_map.begin(), c.member_map.end(), member_map);
+  if (pos_map) std::copy(c.pos_map.begin(), c.pos_map.end(), pos_map);
+  if (arg_map) std::copy(c.arg_map.begin(), c.arg_map.end(), arg_map);
+  if (index_map)
+    for (size_t k = 0; k < c.index_map.size(); ++k) index_map[k] = (char)('a' + c.index_map[k]);
+  if (n_index) *n_index = (int32_t)c.index_map.size();
+  return BES_OK;
+}
+
+int bes_plan_graph(const bes_plan *plan, int32_t which, int32_t *n_nodes, uint8_t *adj,
+                   int32_t *colors) {
+  if (!plan) return fail(BES_E_INVALID, "plan is NULL");
+  const bes::Digraph &g = which ? plan->p.canon.canon_graph : plan->p.canon.induced.g;
+  if (n_nodes) *n_nodes = g.n;
+  if (adj) {
+    auto d = g.dense();
+    std::memcpy(adj, d.data(), d.size());
+  }
+  if (colors) std::copy(g.color.begin(), g.color.end(), colors);
+  return BES_OK;
+}
+
+int bes_check_compliance(int32_t n, const uint8_t *adj, const int32_t *colors) {
+  if (n < 0 || (n > 0 && (!adj || !colors))) return fail(BES_E_INVALID, "bad graph");
+  bes::Digraph g = bes::Digraph::from_dense(n, adj, colors);
+  return bes::check_compliance(g);
+}
+
+int bes_canonical_labeling(int32_t n, const uint8_t *adj, const int32_t *colors, int32_t *label) {
+  if (n < 0 || (n > 0 && (!adj || !colors || !label))) return fail(BES_E_INVALID, "bad graph");
+  bes::Digraph g = bes::Digraph::from_dense(n, adj, colors);
+  std::vector<int> lab = bes::canonical_labeling(g);
+  std::copy(lab.begin(), lab.end(), label);
+  return BES_OK;
+}
+
+int bes_plan_lookup(bes_ctx *ctx, bes_plan *plan, const char *arch) {
+  if (!plan) return fail(BES_E_INVALID, "plan is NULL");
+  return apply_lookup(ctx, plan->p, arch ? arch : kDefaultArch);
+}
+
+int bes_plan_get_config(const bes_plan *plan, bes_config *cfg) {
+  if (!plan || !cfg) return fail(BES_E_INVALID, "NULL argument");
+  *cfg = plan->p.cfg;
+  return BES_OK;
+}
+
+int bes_plan_set_config(bes_plan *plan, const bes_config *cfg) {
+  if (!plan || !cfg) return fail(BES_E_INVALID, "NULL argument");
+  bes_config c = *cfg;
+  if (c.template_id == BES_T_AUTO) c = bes::default_config(plan->p);
+  if (!bes::template_supported(plan->p, c.template_id))
+    return fail(BES_E_UNSUPPORTED, "template cannot evaluate this plan");
+  if (c.template_id == BES_T_GENERIC) {
+    int lanes = c.p[1] > 0 ? c.p[1] : 1;
+    if (lanes > 64 || (lanes & (lanes - 1))) return fail(BES_E_INVALID, "lanes must be 2^k <= 64");
+    if (c.p[0] < 0) return fail(BES_E_INVALID, "negative tile");
+  }
+  plan->p.cfg = c;
+  return BES_OK;
+}
+
+int bes_db_record(bes_ctx *ctx, const char *key, const char *arch, const bes_config *cfg,
+                  double seconds) {
+  if (!ctx || !key || !arch || !cfg) return fail(BES_E_INVALID, "NULL argument");
+  std::string err;
+  int rc = ctx->db.record(key, arch, *cfg, seconds, err);
+  return rc ? fail(rc, err) : BES_OK;
+}
+
+int bes_ctx_stats(const bes_ctx *ctx, int64_t *hits, int64_t *misses) {
+  if (!ctx) return fail(BES_E_INVALID, "ctx is NULL");
+  if (hits) *hits = ctx->db.hits;
+  if (misses) *misses = ctx->db.misses;
+  return BES_OK;
+}
+
+int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *out_ptrs,
+               void *hip_stream) {
+  if (!plan || !src_ptrs || !out_ptrs) return fail(BES_E_INVALID, "NULL argument");
+  const bes::Plan &p = plan->p;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  std::vector<const void *> src(p.n_src);
+  for (int k = 0; k < p.n_src; ++k) src[k] = p.adjoint ? src_ptrs[p.src_from[k]] : src_ptrs[k];
+  for (int k = 0; k < p.n_src; ++k)
+    if (!src[k]) return fail(BES_E_INVALID, "NULL source pointer");
+  for (int s = 0; s < p.n_slots; ++s)
+    if (!out_ptrs[s]) return fail(BES_E_INVALID, "NULL output pointer");
+  const bool f64 = p.spec.dtype == BES_FLOAT64;
+  std::string err;
+  hipError_t e;
+  switch (p.cfg.template_id) {
+    case BES_T_FEM_STREAM: {
+      FemArgs a;
+      int rc = bes::bind_fem(p, src.data(), out_ptrs, a, err);
+      if (rc) return fail(rc, err);
+      e = bes::launch_fem(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, a, p.cfg.p[0], p.cfg.p[1],
+                          stream);
+      if (e != hipSuccess) return hip_fail(e, "FEM-stream launch");
+      return BES_OK;
+    }
+    case BES_T_MFMA: {
+      MfmaArgs a;
+      int rc = bes::bind_mfma(p, src.data(), out_ptrs, a, err);
+      if (rc) return fail(rc, err);
+      e = bes::launch_mfma(a, p.cfg.p[0], p.cfg.p[1], stream);
+      if (e != hipSuccess) return hip_fail(e, "MFMA launch");
+      return BES_OK;
+    }
+    case BES_T_GENERIC: {
+      GenEinsum *g = new (std::nothrow) GenEinsum;
+      if (!g) return fail(BES_E_NOMEM, "out of host memory");
+      int rc = bes::bind_generic_static(p, p.cfg, *g, err);
+      if (rc) {
+        delete g;
+        return fail(rc, err);
+      }
+      e = ensure_generic_dev(p, *g);
+      if (e != hipSuccess) {
+        delete g;
+        return hip_fail(e, "generic descriptor upload");
+      }
+      GenPtrs ptrs;
+      bes::bind_generic_ptrs(p, src.data(), out_ptrs, ptrs);
+      e = bes::launch_generic(f64, (const GenEinsum *)p.gen_dev, *g, ptrs, stream);
+      delete g;
+      if (e != hipSuccess) return hip_fail(e, "generic launch");
+      return BES_OK;
+    }
+    default:
+      return fail(BES_E_UNSUPPORTED, "no kernel template evaluates this plan (dtype " +
+                                         std::string(bes::dtype_name(p.spec.dtype)) + ")");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched launch
+// ---------------------------------------------------------------------------
+
+void bes_batch_destroy(bes_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  if (b->d_table) (void)hipFree(b->d_table);
+  if (b->d_ptrs) (void)hipFree(b->d_ptrs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  if (b->h_ptrs) (void)hipHostFree(b->h_ptrs);
+  delete b;
+}
+
+int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_batch **out) {
+  (void)ctx;
+  if (!out || !plans || count <= 0) return fail(BES_E_INVALID, "bad arguments");
+  *out = nullptr;
+  bes_batch *B = new (std::nothrow) bes_batch;
+  if (!B) return fail(BES_E_NOMEM, "out of host memory");
+  std::vector<GenEinsum> table(count);
+  std::vector<GenItem> items;
+  std::vector<double> cost;
+  std::string err;
+  for (int k = 0; k < count; ++k) {
+    if (!plans[k]) {
+      bes_batch_destroy(B);
+      return fail(BES_E_INVALID, "NULL plan");
+    }
+    const bes::Plan &p = plans[k]->p;
+    bool f64 = p.spec.dtype == BES_FLOAT64;
+    if (k == 0) B->f64 = f64;
+    if (f64 != B->f64) {
+      bes_batch_destroy(B);
+      return fail(BES_E_UNSUPPORTED, "a batch must have one dtype");
+    }
+    bes_config c = p.cfg;
+    if (c.template_id != BES_T_GENERIC) {
+      c.template_id = BES_T_GENERIC;
+      c.p[0] = 256;
+      c.p[1] = 1;
+    }
+    int rc = bes::bind_generic_static(p, c, table[k], err);
+    if (rc) {
+      bes_batch_destroy(B);
+      return fail(rc, err);
+    }
+    B->plans.push_back(&p);
+    const GenEinsum &g = table[k];
+    for (int s = 0; s < g.n_slots; ++s) {
+      int members = g.slot_m1[s] - g.slot_m0[s];
+      for (int64_t f = 0; f < g.out_size; f += g.tile) {
+        GenItem it;
+        it.einsum = k;
+        it.slot = s;
+        it.first = f;
+        it.count = std::min<int64_t>(g.tile, g.out_size - f);
+        items.push_back(it);
+        cost.push_back((double)it.count * (double)std::max<int64_t>(g.con_size, 1) * members *
+                       g.n_ops);
+      }
+    }
+  }
+  // Longest-processing-time first: the dynamic counter then balances the tail.
+  std::vector<int> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<GenItem> sorted;
+  for (int i : order) sorted.push_back(items[i]);
+  B->n_items = (int)sorted.size();
+  hipError_t e;
+  if ((e = hipGetDevice(&B->device)) != hipSuccess ||
+      (e = hipMalloc((void **)&B->d_table, sizeof(GenEinsum) * count)) != hipSuccess ||
+      (e = hipMalloc((void **)&B->d_ptrs, sizeof(GenPtrs) * count)) != hipSuccess ||
+      (e = hipMalloc((void **)&B->d_items, sizeof(GenItem) * std::max(1, B->n_items))) !=
+          hipSuccess ||
+      (e = hipMalloc((void **)&B->d_counters, 2 * sizeof(unsigned))) != hipSuccess ||
+      (e = hipHostMalloc((void **)&B->h_ptrs, sizeof(GenPtrs) * count)) != hipSuccess ||
+      (e = hipMemcpy(B->d_table, table.data(), sizeof(GenEinsum) * count,
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(B->d_items, sorted.data(), sizeof(GenItem) * B->n_items,
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(B->d_counters, 0, 2 * sizeof(unsigned))) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&B->staged, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&B->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
+    bes_batch_destroy(B);
+    return hip_fail(e, "batch setup");
+  }
+  B->last.resize(count);
+  B->grid = std::min(B->n_items, bes::device_cu_count() * 4);
+  B->use_graph = !env_flag("BES_NO_GRAPH");
+  *out = B;
+  return BES_OK;
+}
+
+int bes_batch_launch(bes_batch *B, const void *const *const *src_ptrs, void *const *const *out_ptrs,
+                     void *hip_stream) {
+  if (!B || !src_ptrs || !out_ptrs) return fail(BES_E_INVALID, "NULL argument");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const int count = (int)B->plans.size();
+  std::vector<GenPtrs> cur(count);
+  for (int k = 0; k < count; ++k) {
+    const bes::Plan &p = *B->plans[k];
+    if (!src_ptrs[k] || !out_ptrs[k]) return fail(BES_E_INVALID, "NULL pointer list");
+    std::vector<const void *> src(p.n_src);
+    for (int q = 0; q < p.n_src; ++q) src[q] = p.adjoint ? src_ptrs[k][p.src_from[q]] : src_ptrs[k][q];
+    bes::bind_generic_ptrs(p, src.data(), out_ptrs[k], cur[k]);
+  }
+  hipError_t e;
+  bool changed = !B->have_last ||
+                 std::memcmp(cur.data(), B->last.data(), sizeof(GenPtrs) * count) != 0;
+  if (changed) {
+    // the previous staging copy must have been consumed before it is rewritten
+    if (B->have_last && (e = hipEventSynchronize(B->staged)) != hipSuccess)
+      return hip_fail(e, "batch staging sync");
+    std::memcpy(B->h_ptrs, cur.data(), sizeof(GenPtrs) * count);
+    if ((e = hipMemcpyAsync(B->d_ptrs, B->h_ptrs, sizeof(GenPtrs) * count,
+                            hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = hipEventRecord(B->staged, stream)) != hipSuccess)
+      return hip_fail(e, "batch pointer upload");
+    B->last = cur;
+    B->have_last = true;
+  }
+  if (B->use_graph && !B->exec) {
+    bool ok = hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      hipError_t le = bes::launch_persistent(B->f64, B->d_table, B->d_ptrs, B->d_items, B->n_items,
+                                             B->d_counters, B->grid, B->capture_stream);
+      hipGraph_t g = nullptr;
+      hipError_t ce = hipStreamEndCapture(B->capture_stream, &g);
+      ok = le == hipSuccess && ce == hipSuccess && g;
+      if (ok && hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        ok = false;
+        B->exec = nullptr;
+      }
+      if (ok) B->graph = g;
+      else if (g) (void)hipGraphDestroy(g);
+    }
+    if (!ok) {
+      (void)hipGetLastError();
+      B->use_graph = false;  // fall back to direct persistent launches
+    }
+  }
+  if (B->use_graph && B->exec) {
+    e = hipGraphLaunch(B->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return BES_OK;
+  }
+  e = bes::launch_persistent(B->f64, B->d_table, B->d_ptrs, B->d_items, B->n_items, B->d_counters,
+                             B->grid, stream);
+  if (e != hipSuccess) return hip_fail(e, "persistent launch");
+  return BES_OK;
+}
+
+int bes_adjoint(bes_ctx *ctx, const bes_plan *fwd, int32_t pos, bes_plan **out, int32_t *n_out) {
+  if (!fwd || !out) return fail(BES_E_INVALID, "NULL argument");
+  *out = nullptr;
+  try {
+    bes_plan *P = new bes_plan;
+    std::string err;
+    int nout = 0;
+    int rc = bes::build_adjoint(fwd->p, pos, P->p, nout, err);
+    if (rc) {
+      delete P;
+      return fail(rc, err);
+    }
+    if (n_out) *n_out = nout;
+    rc = apply_lookup(ctx, P->p, kDefaultArch);
+    *out = P;
+    return rc;
+  } catch (const std::bad_alloc &) {
+    return fail(BES_E_NOMEM, "out of host memory");
+  }
+}
+
+}  // extern "C"

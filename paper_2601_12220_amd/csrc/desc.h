@@ -1,0 +1,136 @@
+// Plain-old-data launch descriptors shared by the host planner and the HIP
+// kernels.  Host code fills them after binding the caller's buffers to the
+// canonical operand slots; kernels read them from kernel arguments or from a
+// device-resident table.
+#pragma once
+
+#include <stdint.h>
+
+// ---------------------------------------------------------------------------
+// FEM-stream template: per-element ("stream") operands U and G, a small
+// operand S that carries no stream index.  Per element e and member m:
+//   T_g[r, i]        = sum_j S_g[r, i, j] * U_g[e, j]        (stage 1)
+//   out_m[e, x, i]   = sum_r G_m[e, x, r] * T_g[r, i]        (stage 2)
+// where g is the stage-1 group of member m (members whose S and U are the
+// same argument share T: the batch-level hoisting of a shared product).
+// Without G (two-operand einsums) out_m[e, i] = T_g[0, i].
+// ---------------------------------------------------------------------------
+#define BES_FEM_MAX_MEMBERS 8
+#define BES_FEM_MAX_GROUPS 8
+
+enum { FEM_SRC_ARRAY = 0, FEM_SRC_ELEMENTWISE = 1, FEM_SRC_TET = 2, FEM_SRC_NONE = 3 };
+
+typedef struct FemSrc {
+  const void *p0;
+  const void *p1;   // second source of ELEMENTWISE (S1) or NULL
+  int64_t off0, off1;
+  int64_t s0[3];    // strides of source 0 along (e, x, r) for G, (e, j) for U;
+                    // for TET: (e, vertex, coordinate) strides of V[e, 4, 3]
+  int64_t s1[3];    // for TET, s1[0] = 1 when the einsum reads the Jacobian
+                    // operand with its last two axes swapped, (e, r, x)
+  int32_t kind;     // FEM_SRC_*
+  int32_t op;       // BES_OP_*
+  double alpha, beta;
+} FemSrc;
+
+typedef struct FemMember {
+  FemSrc g;         // kind FEM_SRC_NONE when the einsum has no G operand
+  void *out;
+  int64_t oe, ox, oi;  // output strides along (e, x, i)
+  int32_t group;
+  int32_t pad;
+} FemMember;
+
+typedef struct FemGroup {
+  const void *S;    // dense [NR][NI][NJ] in role order
+  FemSrc u;
+  int32_t m0, m1;   // members [m0, m1) use this group
+} FemGroup;
+
+typedef struct FemArgs {
+  int64_t E;                 // number of stream elements
+  int32_t n_groups, n_members;
+  FemGroup grp[BES_FEM_MAX_GROUPS];
+  FemMember mem[BES_FEM_MAX_MEMBERS];
+} FemArgs;
+
+// ---------------------------------------------------------------------------
+// Generic template: any batched einsum with up to 4 operands, 8 output and 8
+// contracted indices.  Output element o of slot s is
+//   sum over members m of slot s, sum over contracted c, prod_k M(A^{m,k})[...]
+// (a slot is one output; regular plans have one member per slot, adjoint
+// plans may sum several).
+// ---------------------------------------------------------------------------
+#define BES_GEN_MAX_OPS 4
+#define BES_GEN_MAX_IDX 8
+#define BES_GEN_MAX_B 16
+
+// GEN_ELEMENTWISE reads one source, GEN_ELEMENTWISE2 adds a second source;
+// GEN_TET is S0[pos0] - S0[pos1] (both positions in the first source).
+enum { GEN_ARRAY = 0, GEN_ELEMENTWISE = 1, GEN_TET = 2, GEN_ELEMENTWISE2 = 3 };
+
+typedef struct GenLayout {
+  int32_t kind, op;
+  double alpha, beta;
+  int64_t off0, off1;
+  int64_t so0[BES_GEN_MAX_IDX], sc0[BES_GEN_MAX_IDX];  // source 0 strides per
+  int64_t so1[BES_GEN_MAX_IDX], sc1[BES_GEN_MAX_IDX];  // output / contracted idx
+} GenLayout;
+
+typedef struct GenEinsum {
+  int32_t n_ops, n_out, n_con, b, n_slots;
+  int32_t lanes;             // lanes cooperating on one output (1..64)
+  int32_t tile;              // outputs per work item
+  int32_t pad;
+  int64_t out_ext[BES_GEN_MAX_IDX], con_ext[BES_GEN_MAX_IDX];
+  int64_t out_size, con_size;
+  int64_t ostride[BES_GEN_MAX_IDX];
+  int32_t layout[BES_GEN_MAX_B][BES_GEN_MAX_OPS];  // layout id per (member, op)
+  int32_t slot_of[BES_GEN_MAX_B];                  // member -> output slot
+  int32_t slot_m0[BES_GEN_MAX_B], slot_m1[BES_GEN_MAX_B];  // members of slot,
+  int32_t slot_members[BES_GEN_MAX_B];             // listed contiguously
+  int32_t n_layouts;
+  int32_t pad2;
+  GenLayout lay[BES_GEN_MAX_B * BES_GEN_MAX_OPS];
+} GenEinsum;
+
+typedef struct GenPtrs {
+  const void *src[BES_GEN_MAX_B][BES_GEN_MAX_OPS][2];
+  void *out[BES_GEN_MAX_B];
+} GenPtrs;
+
+// Work item of the persistent batched launch: one tile of one slot of one
+// einsum.
+typedef struct GenItem {
+  int32_t einsum;   // index into the descriptor table
+  int32_t slot;
+  int64_t first;    // first output element of the tile
+  int64_t count;    // outputs in the tile
+} GenItem;
+
+// ---------------------------------------------------------------------------
+// MFMA template: C_m[M, N] (+)= sum_{members m of the slot} A_m[M, K] B_m[K, N]
+// where each of M, N, K is a group of indices that merges into one strided
+// axis in every operand.  FP32 in, FP32 accumulate.
+// ---------------------------------------------------------------------------
+#define BES_MFMA_MAX_B 8
+
+typedef struct MfmaMember {
+  const float *A;
+  const float *B;
+  int64_t sam, sak;   // A strides (M, K)
+  int64_t sbk, sbn;   // B strides (K, N)
+} MfmaMember;
+
+typedef struct MfmaSlot {
+  float *C;
+  int64_t scm, scn;
+  int32_t m0, m1;     // members [m0, m1) are summed into C
+} MfmaSlot;
+
+typedef struct MfmaArgs {
+  int64_t M, N, K;
+  int32_t n_members, n_slots;
+  MfmaMember mem[BES_MFMA_MAX_B];
+  MfmaSlot slot[BES_MFMA_MAX_B];
+} MfmaArgs;

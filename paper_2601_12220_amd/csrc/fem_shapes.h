@@ -1,0 +1,19 @@
+// Extents (NI, NJ, NR, NX) for which the FEM-stream template is compiled:
+// the local-gradient class of DG-FEM operators on P1..P4 tetrahedra
+// (i = j in {4, 10, 20, 35}, x = r = 3; Section "Batched einsums in DG-FEM
+// Operators"), the same with one output component per member (x absent),
+// and plain element-wise mat-vecs (r and x absent).
+#pragma once
+
+#define BES_FEM_SHAPES(X)                                                  \
+  X(4, 4, 1, 1) X(10, 10, 1, 1) X(20, 20, 1, 1) X(35, 35, 1, 1)            \
+  X(4, 4, 3, 1) X(10, 10, 3, 1) X(20, 20, 3, 1) X(35, 35, 3, 1)            \
+  X(4, 4, 3, 3) X(10, 10, 3, 3) X(20, 20, 3, 3) X(35, 35, 3, 3)
+
+inline bool fem_shape_compiled(bool /*f64*/, int ni, int nj, int nr, int nx) {
+#define BES_FEM_MATCH(a, b, c, d) \
+  if (ni == (a) && nj == (b) && nr == (c) && nx == (d)) return true;
+  BES_FEM_SHAPES(BES_FEM_MATCH)
+#undef BES_FEM_MATCH
+  return false;
+}

@@ -1,0 +1,715 @@
+// Template analysis, default configs, binding and the adjoint builder.
+//
+// Role analysis runs on the canonical form (Algorithm
+// "CanonicalizeBatchedEinsum" output), so every isomorphic registration gets
+// the same template and the same tuning record; binding then routes each
+// canonical operand slot to the caller's buffer through the substitution maps
+// (the composition step of Algorithm "IdentifyAsEinsum").
+#include "plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+#include "../fem_shapes.h"
+
+namespace bes {
+
+// The MFMA template is selected by default only once its kernel is built.
+constexpr bool kMfmaTemplateReady = false;
+
+namespace {
+
+bool contains(const std::vector<int> &v, int x) {
+  return std::find(v.begin(), v.end(), x) != v.end();
+}
+
+bool has_repeat(const std::vector<int> &v) {
+  for (size_t a = 0; a < v.size(); ++a)
+    for (size_t b = a + 1; b < v.size(); ++b)
+      if (v[a] == v[b]) return true;
+  return false;
+}
+
+// User argument bound to canonical slot (member k, position j).
+int slot_arg(const Plan &p, int k, int j) {
+  return p.spec.arg(p.canon.member_map[k], p.canon.pos_map[j]);
+}
+
+// Stride of source s of the operand at canonical position j (an argument)
+// along canonical index c (summed over repeated axes; 0 if absent).
+int64_t stride_of(const Plan &p, int arg, int j, int s, int c) {
+  const Operand &o = p.spec.args[arg];
+  int64_t st = 0;
+  const auto &labels = p.canon.form.ins[j];
+  for (int d = 0; d < (int)labels.size(); ++d)
+    if (labels[d] == c) st += o.src_strides[s][d];
+  return st;
+}
+
+// Axis of canonical index c in the operand at canonical position j.
+int axis_of(const Plan &p, int j, int c) {
+  const auto &labels = p.canon.form.ins[j];
+  for (int d = 0; d < (int)labels.size(); ++d)
+    if (labels[d] == c) return d;
+  return -1;
+}
+
+void analyse_fem(Plan &p) {
+  const CanonEinsum &e = p.canon.form;
+  auto fail = [&](const char *why) {
+    p.fem_ok = false;
+    p.fem_why = why;
+  };
+  if (p.adjoint) return fail("adjoint plans sum members");
+  if (p.spec.dtype != BES_FLOAT32 && p.spec.dtype != BES_FLOAT64) return fail("dtype");
+  if (e.b > BES_FEM_MAX_MEMBERS) return fail("b > 8");
+  if (e.n != 2 && e.n != 3) return fail("n not in {2,3}");
+  for (const auto &l : e.ins)
+    if (has_repeat(l)) return fail("repeated index");
+  // Stream index: the output index of strictly largest extent.
+  int E = -1;
+  int64_t best = -1;
+  bool tie = false;
+  for (int c : e.out) {
+    if (e.extent[c] > best) {
+      best = e.extent[c];
+      E = c;
+      tie = false;
+    } else if (e.extent[c] == best) {
+      tie = true;
+    }
+  }
+  if (E < 0) return fail("no output index");
+  for (int c = 0; c < (int)e.extent.size(); ++c)
+    if (c != E && e.extent[c] >= best) tie = true;
+  if (tie) return fail("no unique stream index");
+  FemRoles R;
+  R.e = E;
+  std::vector<int> with_e, without_e;
+  for (int j = 0; j < e.n; ++j) (contains(e.ins[j], E) ? with_e : without_e).push_back(j);
+  if (without_e.size() != 1) return fail("need exactly one operand without the stream index");
+  R.posS = without_e[0];
+  const auto &S = e.ins[R.posS];
+  auto in_out = [&](int c) { return contains(e.out, c); };
+  if (e.n == 2) {
+    R.posU = with_e[0];
+    const auto &U = e.ins[R.posU];
+    if (U.size() != 2 || S.size() != 2) return fail("2-operand form needs S[i,j], U[e,j]");
+    int j = U[0] == E ? U[1] : U[0];
+    if (!contains(S, j) || in_out(j)) return fail("U's contracted index must be in S");
+    int i = S[0] == j ? S[1] : S[0];
+    if (!in_out(i) || contains(U, i)) return fail("S's free index must be an output index");
+    if (e.out.size() != 2) return fail("output must be (e, i)");
+    R.i = i;
+    R.j = j;
+  } else {
+    // Which e-operand is U = {e, j}: j shared with S only and contracted.
+    // When both qualify (G = {e, r} has the same pattern), take the one whose
+    // argument repeats across the most members, so that stage 1 is hoisted
+    // out of the member loop; then the larger contracted extent (cheaper
+    // stage 2); then the lower canonical position.
+    int cand = -1;
+    int best_distinct = 1 << 30;
+    int64_t best_ext = -1;
+    for (int k = 0; k < 2; ++k) {
+      const auto &X = e.ins[with_e[k]];
+      const auto &Y = e.ins[with_e[1 - k]];
+      if (X.size() != 2) continue;
+      int j = X[0] == E ? X[1] : X[0];
+      if (!(contains(S, j) && !in_out(j) && !contains(Y, j))) continue;
+      std::vector<int> distinct;
+      for (int m = 0; m < e.b; ++m) {
+        int a = e.arg(m, with_e[k]);
+        if (!contains(distinct, a)) distinct.push_back(a);
+      }
+      int nd = (int)distinct.size();
+      if (nd < best_distinct || (nd == best_distinct && e.extent[j] > best_ext)) {
+        best_distinct = nd;
+        best_ext = e.extent[j];
+        cand = k;
+        R.j = j;
+      }
+    }
+    if (cand < 0) return fail("no U[e,j] operand");
+    R.posU = with_e[cand];
+    R.posG = with_e[1 - cand];
+    const auto &G = e.ins[R.posG];
+    if (S.size() != 3) return fail("3-operand form needs S[r,i,j]");
+    int r = -1, x = -1;
+    for (int c : G) {
+      if (c == E) continue;
+      if (contains(S, c) && !in_out(c)) {
+        if (r >= 0) return fail("G has two contracted indices");
+        r = c;
+      } else if (in_out(c) && !contains(S, c)) {
+        if (x >= 0) return fail("G has two free indices");
+        x = c;
+      } else {
+        return fail("G index with unsupported role");
+      }
+    }
+    if (r < 0) return fail("G lacks a contracted index shared with S");
+    int i = -1;
+    for (int c : S)
+      if (c != r && c != R.j) i = c;
+    if (i < 0 || !in_out(i)) return fail("S's free index must be an output index");
+    if (e.out.size() != (size_t)(x >= 0 ? 3 : 2)) return fail("output must be (e, [x,] i)");
+    if (G.size() != (size_t)(x >= 0 ? 3 : 2)) return fail("G must be (e, [x,] r)");
+    R.i = i;
+    R.r = r;
+    R.x = x;
+  }
+  R.NI = (int)e.extent[R.i];
+  R.NJ = (int)e.extent[R.j];
+  R.NR = R.r >= 0 ? (int)e.extent[R.r] : 1;
+  R.NX = R.x >= 0 ? (int)e.extent[R.x] : 1;
+  if (!fem_shape_compiled(p.spec.dtype == BES_FLOAT64, R.NI, R.NJ, R.NR, R.NX))
+    return fail("no compiled instantiation for these extents");
+  // Operand kinds and the dense role-order layout of S.
+  for (int k = 0; k < e.b; ++k) {
+    const Operand &s = p.spec.args[slot_arg(p, k, R.posS)];
+    if (s.kind != BES_ARRAY && s.kind != BES_VIEW) return fail("S must be an array or view");
+    int64_t sr = R.r >= 0 ? stride_of(p, slot_arg(p, k, R.posS), R.posS, 0, R.r) : 0;
+    int64_t si = stride_of(p, slot_arg(p, k, R.posS), R.posS, 0, R.i);
+    int64_t sj = stride_of(p, slot_arg(p, k, R.posS), R.posS, 0, R.j);
+    if (sj != 1 || si != R.NJ || (R.r >= 0 && sr != (int64_t)R.NI * R.NJ))
+      return fail("S is not dense in (r, i, j) order");
+    const Operand &u = p.spec.args[slot_arg(p, k, R.posU)];
+    if (u.kind == BES_TET_JACOBIAN) return fail("U cannot be a Jacobian operand");
+    if (R.posG >= 0) {
+      const Operand &g = p.spec.args[slot_arg(p, k, R.posG)];
+      if (g.kind == BES_TET_JACOBIAN && (R.NX != 3 || R.NR != 3))
+        return fail("Jacobian operand needs x = r = 3");
+    }
+  }
+  p.fem = R;
+  p.fem_ok = true;
+  p.fem_why.clear();
+}
+
+// Merged stride of a group of canonical indices (in merge order) for one
+// operand; false if the group does not merge into one strided axis.
+bool merge_group(const Plan &p, int arg, int j, const std::vector<int> &grp,
+                 const std::vector<int64_t> &ext, int64_t &stride) {
+  if (grp.empty()) {
+    stride = 0;
+    return true;
+  }
+  for (size_t k = 0; k + 1 < grp.size(); ++k) {
+    int64_t a = stride_of(p, arg, j, 0, grp[k]);
+    int64_t b = stride_of(p, arg, j, 0, grp[k + 1]);
+    if (a != b * ext[grp[k + 1]]) return false;
+  }
+  stride = stride_of(p, arg, j, 0, grp.back());
+  return true;
+}
+
+bool merge_out(const std::vector<int> &out, const std::vector<int> &grp,
+               const std::vector<int64_t> &ext, int64_t &stride) {
+  // dense row-major output strides in `out` order
+  std::vector<int64_t> st(out.size());
+  int64_t s = 1;
+  for (int d = (int)out.size() - 1; d >= 0; --d) {
+    st[d] = s;
+    s *= ext[out[d]];
+  }
+  auto sof = [&](int c) {
+    for (size_t d = 0; d < out.size(); ++d)
+      if (out[d] == c) return st[d];
+    return (int64_t)0;
+  };
+  for (size_t k = 0; k + 1 < grp.size(); ++k)
+    if (sof(grp[k]) != sof(grp[k + 1]) * ext[grp[k + 1]]) return false;
+  stride = grp.empty() ? 0 : sof(grp.back());
+  return true;
+}
+
+void analyse_mfma(Plan &p) {
+  const CanonEinsum &e = p.canon.form;
+  auto fail = [&](const char *why) {
+    p.mfma_ok = false;
+    p.mfma_why = why;
+  };
+  if (p.spec.dtype != BES_FLOAT32) return fail("MFMA template is FP32");
+  if (e.n != 2) return fail("n != 2");
+  if (e.b > BES_MFMA_MAX_B) return fail("b > 8");
+  if (e.out.empty()) return fail("scalar output");
+  for (const auto &l : e.ins)
+    if (has_repeat(l)) return fail("repeated index");
+  const int nidx = (int)e.extent.size();
+  for (int c = 0; c < nidx; ++c) {
+    int cnt = contains(e.ins[0], c) + contains(e.ins[1], c) + contains(e.out, c);
+    if (cnt != 2) return fail("not a pure two-operand contraction");
+  }
+  MfmaRoles R;
+  R.posA = contains(e.ins[0], e.out[0]) ? 0 : 1;
+  R.posB = 1 - R.posA;
+  for (int c : e.out) (contains(e.ins[R.posA], c) ? R.Mi : R.Ni).push_back(c);
+  for (int c : e.ins[R.posA])
+    if (contains(e.ins[R.posB], c)) R.Ki.push_back(c);
+  if (R.Ni.empty() || R.Ki.empty()) return fail("degenerate GEMM shape");
+  // Output must be (M group, N group) or (N group, M group) as one block each.
+  std::vector<int> mn = R.Mi, nm = R.Ni;
+  mn.insert(mn.end(), R.Ni.begin(), R.Ni.end());
+  nm.insert(nm.end(), R.Mi.begin(), R.Mi.end());
+  if (e.out == mn) R.c_mn = true;
+  else if (e.out == nm) R.c_mn = false;
+  else return fail("output interleaves M and N indices");
+  R.M = R.N = R.K = 1;
+  for (int c : R.Mi) R.M *= e.extent[c];
+  for (int c : R.Ni) R.N *= e.extent[c];
+  for (int c : R.Ki) R.K *= e.extent[c];
+  if (R.M % 64 || R.N % 64 || R.K % 16 || R.M < 64 || R.N < 64)
+    return fail("M, N not multiples of 64 or K of 16");
+  int64_t st;
+  for (int k = 0; k < e.b; ++k) {
+    int a = slot_arg(p, k, R.posA), b = slot_arg(p, k, R.posB);
+    for (int arg : {a, b}) {
+      const Operand &o = p.spec.args[arg];
+      if (o.kind != BES_ARRAY && o.kind != BES_VIEW) return fail("MFMA operands must be arrays or views");
+    }
+    if (!merge_group(p, a, R.posA, R.Mi, e.extent, st) ||
+        !merge_group(p, a, R.posA, R.Ki, e.extent, st) ||
+        !merge_group(p, b, R.posB, R.Ki, e.extent, st) ||
+        !merge_group(p, b, R.posB, R.Ni, e.extent, st))
+      return fail("an index group does not merge into one strided axis");
+  }
+  p.mf = R;
+  p.mfma_ok = true;
+  p.mfma_why.clear();
+}
+
+}  // namespace
+
+bool template_supported(const Plan &p, int t) {
+  switch (t) {
+    case BES_T_FEM_STREAM: return p.fem_ok;
+    case BES_T_MFMA: return p.mfma_ok && kMfmaTemplateReady;
+    case BES_T_GENERIC:
+      return (p.spec.dtype == BES_FLOAT32 || p.spec.dtype == BES_FLOAT64) &&
+             p.spec.b <= BES_GEN_MAX_B && p.spec.n <= BES_GEN_MAX_OPS &&
+             (int)p.canon.form.out.size() <= BES_GEN_MAX_IDX &&
+             (int)p.canon.form.extent.size() - (int)p.canon.form.out.size() <= BES_GEN_MAX_IDX;
+    default: return false;
+  }
+}
+
+bes_config default_config(const Plan &p) {
+  bes_config c{};
+  if (p.mfma_ok && kMfmaTemplateReady) {
+    c.template_id = BES_T_MFMA;
+    c.p[0] = 128;
+    c.p[1] = 128;
+  } else if (p.fem_ok) {
+    c.template_id = BES_T_FEM_STREAM;
+    c.p[0] = 256;
+    c.p[1] = 4;
+  } else if (template_supported(p, BES_T_GENERIC)) {
+    c.template_id = BES_T_GENERIC;
+    c.p[0] = 256;
+    c.p[1] = 1;
+  } else {
+    c.template_id = BES_T_AUTO;  // nothing evaluates this plan
+  }
+  return c;
+}
+
+int build_plan(Plan &p, std::string &err) {
+  int rc = canonicalize(p.spec, p.canon, err);
+  if (rc) return rc;
+  p.key = key_string(p.canon.form);
+  p.tuple = tuple_string(p.canon.form);
+  if (p.slot_of_member.empty()) {
+    p.slot_of_member.resize(p.spec.b);
+    for (int i = 0; i < p.spec.b; ++i) p.slot_of_member[i] = i;
+    p.n_slots = p.spec.b;
+  }
+  p.src_base.resize(p.spec.args.size());
+  p.n_src = 0;
+  for (size_t a = 0; a < p.spec.args.size(); ++a) {
+    p.src_base[a] = p.n_src;
+    p.n_src += p.spec.args[a].nsrc;
+  }
+  analyse_fem(p);
+  analyse_mfma(p);
+  // A plan no template can evaluate (e.g. an integer dtype) still has a
+  // canonical form and a key; launching it reports BES_E_UNSUPPORTED.
+  p.cfg = default_config(p);
+  return BES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Binding
+// ---------------------------------------------------------------------------
+
+namespace {
+
+void fill_src(const Plan &p, int arg, int j, const std::vector<int> &roles,
+              const void *const *src, FemSrc &f) {
+  const Operand &o = p.spec.args[arg];
+  std::memset(&f, 0, sizeof f);
+  f.p0 = src[p.src_base[arg]];
+  f.p1 = o.nsrc > 1 ? src[p.src_base[arg] + 1] : nullptr;
+  f.off0 = o.src_offset[0];
+  f.off1 = o.nsrc > 1 ? o.src_offset[1] : 0;
+  f.op = o.op;
+  f.alpha = o.alpha;
+  f.beta = o.beta;
+  if (o.kind == BES_TET_JACOBIAN) {
+    f.kind = FEM_SRC_TET;
+    for (int k = 0; k < 3; ++k) f.s0[k] = o.src_strides[0][k];  // V[e, vertex, coord]
+    // The operand's axis order is (e, x, r); roles (e, x, r) of the kernel may
+    // be swapped relative to it: encode with the sign of s1[0].
+    int ax = axis_of(p, j, roles[1]);
+    f.s1[0] = (ax == 2) ? 1 : 0;  // 1: kernel x is the operand's r axis
+    return;
+  }
+  f.kind = o.kind == BES_ELEMENTWISE ? FEM_SRC_ELEMENTWISE : FEM_SRC_ARRAY;
+  for (size_t k = 0; k < roles.size(); ++k) {
+    if (roles[k] < 0) continue;
+    f.s0[k] = stride_of(p, arg, j, 0, roles[k]);
+    if (o.nsrc > 1) f.s1[k] = stride_of(p, arg, j, 1, roles[k]);
+  }
+}
+
+}  // namespace
+
+int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a,
+             std::string &err) {
+  if (!p.fem_ok) {
+    err = "plan is not FEM-stream compatible: " + p.fem_why;
+    return BES_E_UNSUPPORTED;
+  }
+  const FemRoles &R = p.fem;
+  const CanonEinsum &e = p.canon.form;
+  std::memset(&a, 0, sizeof a);
+  a.E = e.extent[R.e];
+  // Stage-1 groups: canonical members with the same (S, U) arguments, kept
+  // contiguous by ordering members by group.
+  std::vector<std::pair<int, int>> keys;
+  std::vector<int> group_of(e.b);
+  for (int k = 0; k < e.b; ++k) {
+    std::pair<int, int> key(slot_arg(p, k, R.posS), slot_arg(p, k, R.posU));
+    auto it = std::find(keys.begin(), keys.end(), key);
+    if (it == keys.end()) {
+      group_of[k] = (int)keys.size();
+      keys.push_back(key);
+    } else {
+      group_of[k] = (int)(it - keys.begin());
+    }
+  }
+  a.n_groups = (int)keys.size();
+  a.n_members = e.b;
+  // output dense row-major strides along (e, x, i)
+  std::vector<int64_t> ost(e.out.size());
+  {
+    int64_t s = 1;
+    for (int d = (int)e.out.size() - 1; d >= 0; --d) {
+      ost[d] = s;
+      s *= e.extent[e.out[d]];
+    }
+  }
+  auto ostride = [&](int c) -> int64_t {
+    for (size_t d = 0; d < e.out.size(); ++d)
+      if (e.out[d] == c) return ost[d];
+    return 0;
+  };
+  int m = 0;
+  for (int g = 0; g < a.n_groups; ++g) {
+    FemGroup &G = a.grp[g];
+    G.S = src[p.src_base[keys[g].first]];
+    const Operand &so = p.spec.args[keys[g].first];
+    G.S = (const char *)G.S + so.src_offset[0] * (p.spec.dtype == BES_FLOAT64 ? 8 : 4);
+    int k0 = -1;
+    for (int k = 0; k < e.b; ++k)
+      if (group_of[k] == g) {
+        k0 = k;
+        break;
+      }
+    fill_src(p, keys[g].second, R.posU, {R.e, R.j}, src, G.u);
+    G.m0 = m;
+    for (int k = 0; k < e.b; ++k) {
+      if (group_of[k] != g) continue;
+      FemMember &M = a.mem[m];
+      if (R.posG >= 0) {
+        fill_src(p, slot_arg(p, k, R.posG), R.posG, {R.e, R.x, R.r}, src, M.g);
+      } else {
+        std::memset(&M.g, 0, sizeof M.g);
+        M.g.kind = FEM_SRC_NONE;
+      }
+      M.out = out[p.slot_of_member[p.canon.member_map[k]]];
+      M.oe = ostride(R.e);
+      M.ox = R.x >= 0 ? ostride(R.x) : 0;
+      M.oi = ostride(R.i);
+      M.group = g;
+      ++m;
+    }
+    G.m1 = m;
+    (void)k0;
+  }
+  return BES_OK;
+}
+
+int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std::string &err) {
+  if (!template_supported(p, BES_T_GENERIC)) {
+    err = "generic template limits exceeded";
+    return BES_E_UNSUPPORTED;
+  }
+  const Spec &s = p.spec;
+  std::memset(&g, 0, sizeof g);
+  g.n_ops = s.n;
+  g.b = s.b;
+  g.n_out = (int)s.out.size();
+  std::vector<int> con;
+  for (int c : s.used_indices())
+    if (!contains(s.out, c)) con.push_back(c);
+  g.n_con = (int)con.size();
+  g.out_size = 1;
+  for (int d = g.n_out - 1; d >= 0; --d) {
+    g.out_ext[d] = s.extent[s.out[d]];
+    g.ostride[d] = g.out_size;
+    g.out_size *= g.out_ext[d];
+  }
+  g.con_size = 1;
+  for (int d = 0; d < g.n_con; ++d) {
+    g.con_ext[d] = s.extent[con[d]];
+    g.con_size *= g.con_ext[d];
+  }
+  g.tile = cfg.p[0] > 0 ? cfg.p[0] : 256;
+  g.lanes = cfg.p[1] > 0 ? cfg.p[1] : 1;
+  if (g.lanes > 64 || (g.lanes & (g.lanes - 1))) {
+    err = "lanes per output must be a power of two <= 64";
+    return BES_E_INVALID;
+  }
+  g.n_layouts = 0;
+  for (int m = 0; m < s.b; ++m) {
+    for (int j = 0; j < s.n; ++j) {
+      int arg = s.arg(m, j);
+      const Operand &o = s.args[arg];
+      GenLayout L;
+      std::memset(&L, 0, sizeof L);
+      L.op = o.op;
+      L.alpha = o.alpha;
+      L.beta = o.beta;
+      auto put = [&](int64_t *so, int64_t *sc, int d, int64_t st) {
+        int c = s.ins[j][d];
+        for (int q = 0; q < g.n_out; ++q)
+          if (s.out[q] == c) so[q] += st;
+        for (int q = 0; q < g.n_con; ++q)
+          if (con[q] == c) sc[q] += st;
+      };
+      if (o.kind == BES_TET_JACOBIAN) {
+        // M[e,x,r] = V[e, r+1, x] - V[e, 0, x]
+        L.kind = GEN_TET;
+        int64_t se = o.src_strides[0][0], sv = o.src_strides[0][1], sc = o.src_strides[0][2];
+        L.off0 = o.src_offset[0] + sv;
+        L.off1 = o.src_offset[0];
+        put(L.so0, L.sc0, 0, se);
+        put(L.so0, L.sc0, 1, sc);
+        put(L.so0, L.sc0, 2, sv);
+        put(L.so1, L.sc1, 0, se);
+        put(L.so1, L.sc1, 1, sc);
+      } else {
+        L.kind = o.kind != BES_ELEMENTWISE ? GEN_ARRAY
+                 : (o.nsrc > 1 ? GEN_ELEMENTWISE2 : GEN_ELEMENTWISE);
+        L.off0 = o.src_offset[0];
+        for (int d = 0; d < o.ndim; ++d) put(L.so0, L.sc0, d, o.src_strides[0][d]);
+        if (o.nsrc > 1) {
+          L.off1 = o.src_offset[1];
+          for (int d = 0; d < o.ndim; ++d) put(L.so1, L.sc1, d, o.src_strides[1][d]);
+        }
+      }
+      int id = -1;
+      for (int q = 0; q < g.n_layouts; ++q)
+        if (!std::memcmp(&g.lay[q], &L, sizeof L)) {
+          id = q;
+          break;
+        }
+      if (id < 0) {
+        id = g.n_layouts++;
+        g.lay[id] = L;
+      }
+      g.layout[m][j] = id;
+    }
+  }
+  g.n_slots = p.n_slots;
+  int q = 0;
+  for (int sl = 0; sl < p.n_slots; ++sl) {
+    g.slot_m0[sl] = q;
+    for (int m = 0; m < s.b; ++m)
+      if (p.slot_of_member[m] == sl) g.slot_members[q++] = m;
+    g.slot_m1[sl] = q;
+  }
+  for (int m = 0; m < s.b; ++m) g.slot_of[m] = p.slot_of_member[m];
+  return BES_OK;
+}
+
+int bind_generic_ptrs(const Plan &p, const void *const *src, void *const *out, GenPtrs &ptrs) {
+  std::memset(&ptrs, 0, sizeof ptrs);
+  const Spec &s = p.spec;
+  for (int m = 0; m < s.b; ++m)
+    for (int j = 0; j < s.n; ++j) {
+      int arg = s.arg(m, j);
+      ptrs.src[m][j][0] = src[p.src_base[arg]];
+      ptrs.src[m][j][1] = s.args[arg].nsrc > 1 ? src[p.src_base[arg] + 1] : src[p.src_base[arg]];
+    }
+  for (int sl = 0; sl < p.n_slots; ++sl) ptrs.out[sl] = out[sl];
+  return BES_OK;
+}
+
+int bind_mfma(const Plan &p, const void *const *src, void *const *out, MfmaArgs &a,
+              std::string &err) {
+  if (!p.mfma_ok) {
+    err = "plan is not MFMA compatible: " + p.mfma_why;
+    return BES_E_UNSUPPORTED;
+  }
+  const MfmaRoles &R = p.mf;
+  const CanonEinsum &e = p.canon.form;
+  std::memset(&a, 0, sizeof a);
+  a.M = R.M;
+  a.N = R.N;
+  a.K = R.K;
+  a.n_members = e.b;
+  a.n_slots = p.n_slots;
+  // members ordered by slot so that each slot is a contiguous range
+  std::vector<int> order;
+  for (int sl = 0; sl < p.n_slots; ++sl)
+    for (int k = 0; k < e.b; ++k)
+      if (p.slot_of_member[p.canon.member_map[k]] == sl) order.push_back(k);
+  int m = 0;
+  for (int sl = 0; sl < p.n_slots; ++sl) {
+    MfmaSlot &S = a.slot[sl];
+    S.C = (float *)out[sl];
+    int64_t cm, cn;
+    merge_out(e.out, R.Mi, e.extent, cm);
+    merge_out(e.out, R.Ni, e.extent, cn);
+    S.scm = cm;
+    S.scn = cn;
+    S.m0 = m;
+    for (int k : order) {
+      if (p.slot_of_member[p.canon.member_map[k]] != sl) continue;
+      MfmaMember &M = a.mem[m++];
+      int aa = slot_arg(p, k, R.posA), bb = slot_arg(p, k, R.posB);
+      M.A = (const float *)src[p.src_base[aa]] + p.spec.args[aa].src_offset[0];
+      M.B = (const float *)src[p.src_base[bb]] + p.spec.args[bb].src_offset[0];
+      merge_group(p, aa, R.posA, R.Mi, e.extent, M.sam);
+      merge_group(p, aa, R.posA, R.Ki, e.extent, M.sak);
+      merge_group(p, bb, R.posB, R.Ki, e.extent, M.sbk);
+      merge_group(p, bb, R.posB, R.Ni, e.extent, M.sbn);
+    }
+    S.m1 = m;
+  }
+  return BES_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint
+// ---------------------------------------------------------------------------
+
+int build_adjoint(const Plan &fwd, int pos, Plan &adj, int &n_out, std::string &err) {
+  const Spec &f = fwd.spec;
+  if (pos < 0 || pos >= f.n) {
+    err = "position out of range";
+    return BES_E_INVALID;
+  }
+  const auto &W = f.ins[pos];
+  if (has_repeat(W)) {
+    err = "adjoint of a position with a repeated index is not supported";
+    return BES_E_UNSUPPORTED;
+  }
+  for (int c : W) {
+    bool found = contains(f.out, c);
+    for (int m = 0; m < f.n && !found; ++m)
+      if (m != pos && contains(f.ins[m], c)) found = true;
+    if (!found) {
+      err = "adjoint would broadcast over an index used only by this position";
+      return BES_E_UNSUPPORTED;
+    }
+  }
+  // Output slots: distinct arguments at `pos`, in order of first occurrence.
+  std::vector<int> slot_args;
+  std::vector<int> slot_of(f.b);
+  for (int i = 0; i < f.b; ++i) {
+    int a = f.arg(i, pos);
+    auto it = std::find(slot_args.begin(), slot_args.end(), a);
+    if (it == slot_args.end()) {
+      slot_of[i] = (int)slot_args.size();
+      slot_args.push_back(a);
+    } else {
+      slot_of[i] = (int)(it - slot_args.begin());
+    }
+  }
+  n_out = (int)slot_args.size();
+  // Arguments of the adjoint: G_0..G_{b-1}, then the forward arguments used at
+  // positions != pos, in forward order.
+  std::vector<int> keep(f.args.size(), -1);
+  std::vector<bes_operand> args;
+  std::vector<int> src_from;
+  for (int i = 0; i < f.b; ++i) {
+    bes_operand g;
+    std::memset(&g, 0, sizeof g);
+    g.kind = BES_ARRAY;
+    g.dtype = f.dtype;
+    g.ndim = (int)f.out.size();
+    g.nsrc = 1;
+    g.alpha = 1.0;
+    for (int d = 0; d < g.ndim; ++d) g.shape[d] = f.extent[f.out[d]];
+    args.push_back(g);
+    src_from.push_back(i);
+  }
+  if (f.out.empty()) {
+    err = "adjoint of a scalar-output einsum is not supported";
+    return BES_E_UNSUPPORTED;
+  }
+  for (int i = 0; i < f.b; ++i)
+    for (int m = 0; m < f.n; ++m)
+      if (m != pos) keep[f.arg(i, m)] = 0;
+  for (size_t a = 0; a < f.args.size(); ++a) {
+    if (keep[a] < 0) continue;
+    keep[a] = (int)args.size();
+    const Operand &o = f.args[a];
+    bes_operand d;
+    std::memset(&d, 0, sizeof d);
+    d.kind = o.kind;
+    d.dtype = o.dtype;
+    d.ndim = o.ndim;
+    d.nsrc = o.nsrc;
+    d.op = o.op;
+    d.alpha = o.alpha;
+    d.beta = o.beta;
+    for (int k = 0; k < o.ndim; ++k) d.shape[k] = o.shape[k];
+    for (int s = 0; s < o.nsrc; ++s) {
+      d.src_offset[s] = o.src_offset[s];
+      for (int k = 0; k < o.ndim; ++k) d.src_strides[s][k] = o.src_strides[s][k];
+      src_from.push_back(f.b + fwd.src_base[a] + s);
+    }
+    args.push_back(d);
+  }
+  std::vector<int32_t> table;
+  std::string nota;
+  for (int c : f.out) nota += char('a' + c);
+  for (int m = 0; m < f.n; ++m) {
+    if (m == pos) continue;
+    nota += ',';
+    for (int c : f.ins[m]) nota += char('a' + c);
+  }
+  nota += "->";
+  for (int c : W) nota += char('a' + c);
+  for (int i = 0; i < f.b; ++i) {
+    table.push_back(i);
+    for (int m = 0; m < f.n; ++m)
+      if (m != pos) table.push_back(keep[f.arg(i, m)]);
+  }
+  adj = Plan();
+  int rc = make_spec(nota.c_str(), f.b, f.n, (int)args.size(), args.data(), table.data(),
+                     adj.spec, err);
+  if (rc) return rc;
+  adj.adjoint = true;
+  adj.slot_of_member = slot_of;
+  adj.n_slots = n_out;
+  adj.src_from = src_from;
+  return build_plan(adj, err);
+}
+
+}  // namespace bes

@@ -1,0 +1,82 @@
+// Plans: a registered batched einsum with its canonical form, tuning config,
+// and the analysis each kernel template needs (roles of the canonical indices
+// and operand positions).  Binding turns a plan plus the caller's pointers
+// into a launch descriptor.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../desc.h"
+#include "canon.h"
+#include "spec.h"
+
+namespace bes {
+
+// FEM-stream roles, on the canonical form (see desc.h for the computation).
+struct FemRoles {
+  int e = -1, i = -1, j = -1, r = -1, x = -1;  // canonical index ordinals
+  int NI = 1, NJ = 1, NR = 1, NX = 1;
+  int posS = -1, posU = -1, posG = -1;         // canonical positions
+};
+
+// MFMA roles: C[M, N] = A[M, K] B[K, N] with merged index groups.
+struct MfmaRoles {
+  std::vector<int> Mi, Ni, Ki;  // canonical index ordinals, in merge order
+  int posA = -1, posB = -1;
+  bool c_mn = true;             // output order is (M group, N group)
+  int64_t M = 0, N = 0, K = 0;
+};
+
+struct Plan {
+  Spec spec;
+  Canonical canon;
+  std::string key, tuple;
+  bes_config cfg{};
+  bool cfg_from_db = false;
+
+  bool fem_ok = false;
+  std::string fem_why;
+  FemRoles fem;
+  bool mfma_ok = false;
+  std::string mfma_why;
+  MfmaRoles mf;
+
+  // Output slots: member (user order) -> slot.  Regular plans: identity.
+  // Adjoint plans sum the members of a slot.
+  std::vector<int> slot_of_member;
+  int n_slots = 0;
+  // Flattened source pointers: arg a's sources start at src_base[a].
+  std::vector<int> src_base;
+  int n_src = 0;
+  // For adjoint plans: this plan's flat source k is the caller's src_from[k].
+  std::vector<int> src_from;
+  bool adjoint = false;
+
+  // Device copy of the generic descriptor (created on first generic launch).
+  mutable void *gen_dev = nullptr;
+  mutable int gen_dev_device = -1;
+  mutable bes_config gen_dev_cfg{};
+};
+
+// Analyse a registered spec: canonicalize, fill roles, default config.
+int build_plan(Plan &p, std::string &err);
+
+// Templates able to evaluate the plan.
+bool template_supported(const Plan &p, int template_id);
+bes_config default_config(const Plan &p);
+
+// Binders.  `src` are the plan's flat source pointers (after src_from
+// remapping), `out` one pointer per slot.
+int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a,
+             std::string &err);
+int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std::string &err);
+int bind_generic_ptrs(const Plan &p, const void *const *src, void *const *out, GenPtrs &ptrs);
+int bind_mfma(const Plan &p, const void *const *src, void *const *out, MfmaArgs &a,
+              std::string &err);
+
+// Build the adjoint plan of position `pos` (see bes_adjoint in bes.h).
+int build_adjoint(const Plan &fwd, int pos, Plan &adj, int &n_out, std::string &err);
+
+}  // namespace bes

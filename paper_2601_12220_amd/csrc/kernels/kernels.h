@@ -1,0 +1,34 @@
+// Launchers of the HIP kernel templates (gfx950).  Each returns hipSuccess or
+// the HIP error of the failed call; none synchronizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../desc.h"
+
+namespace bes {
+
+// Compute units of the current device (cached per device).
+int device_cu_count();
+
+// FEM-stream template.  `block` threads per block, `blocks_per_cu` resident
+// blocks per compute unit for the grid-stride loop.
+hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, int block,
+                      int blocks_per_cu, hipStream_t stream);
+
+// Generic template: one launch over (slot, tile) pairs.  `dev` is the device
+// copy of `host`.
+hipError_t launch_generic(bool f64, const GenEinsum *dev, const GenEinsum &host,
+                          const GenPtrs &ptrs, hipStream_t stream);
+
+// Persistent batched launch: blocks pull GenItems off a device counter.
+// `table`/`ptrs` are device arrays indexed by einsum; counters[2] must be zero
+// before the first launch and are left zero by every launch.
+hipError_t launch_persistent(bool f64, const GenEinsum *table, const GenPtrs *ptrs,
+                             const GenItem *items, int n_items, unsigned *counters,
+                             int grid, hipStream_t stream);
+
+// MFMA dense-contraction template (FP32).
+hipError_t launch_mfma(const MfmaArgs &a, int tile_m, int tile_n, hipStream_t stream);
+
+}  // namespace bes
