@@ -263,10 +263,18 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
   hipStream_t stream = (hipStream_t)hip_stream;
   std::vector<const void *> src(p.n_src);
   for (int k = 0; k < p.n_src; ++k) src[k] = p.adjoint ? src_ptrs[p.src_from[k]] : src_ptrs[k];
-  for (int k = 0; k < p.n_src; ++k)
-    if (!src[k]) return fail(BES_E_INVALID, "NULL source pointer");
+  // NULL is accepted only for empty operands and outputs.
+  for (size_t a = 0; a < p.spec.args.size(); ++a) {
+    const bes::Operand &o = p.spec.args[a];
+    int64_t sz = 1;
+    for (int d = 0; d < o.ndim; ++d) sz *= o.shape[d];
+    for (int s = 0; s < o.nsrc; ++s)
+      if (!src[p.src_base[a] + s] && sz != 0) return fail(BES_E_INVALID, "NULL source pointer");
+  }
+  int64_t out_size = 1;
+  for (int c : p.spec.out) out_size *= p.spec.extent[c];
   for (int s = 0; s < p.n_slots; ++s)
-    if (!out_ptrs[s]) return fail(BES_E_INVALID, "NULL output pointer");
+    if (!out_ptrs[s] && out_size != 0) return fail(BES_E_INVALID, "NULL output pointer");
   const bool f64 = p.spec.dtype == BES_FLOAT64;
   std::string err;
   hipError_t e;
