@@ -107,7 +107,8 @@ enum bes_template {
   BES_T_AUTO = 0,        /* let the planner pick */
   BES_T_FEM_STREAM = 1,  /* per-element operands streamed from HBM, small
                             shared operand uniform per wave; p[0] = elements
-                            per block (64..512), p[1] = blocks per CU */
+                            per tile (64: one wave), p[1] = resident
+                            one-wave blocks per CU (1..32) */
   BES_T_GENERIC = 2,     /* any batched einsum; p[0] = outputs per tile,
                             p[1] = lanes per output (1,2,4,...,64) */
   BES_T_MFMA = 3         /* dense contraction on MFMA (FP32 in, FP32 acc);

@@ -62,7 +62,11 @@ def _load():
                                      i32p, i64p, dpp, ctypes.c_longlong, i64p, dp]
     lib.oracle_einsum_grad.argtypes = [ctypes.c_int, i32p, i32p, ctypes.c_int,
                                        i32p, i64p, dpp, dp, ctypes.c_int, dp]
-    for f in (lib.oracle_einsum, lib.oracle_einsum_at, lib.oracle_einsum_grad):
+    lib.oracle_einsum_grad_at.argtypes = [ctypes.c_int, i32p, i32p, ctypes.c_int,
+                                          i32p, i64p, dpp, dp, ctypes.c_int,
+                                          ctypes.c_longlong, i64p, dp]
+    for f in (lib.oracle_einsum, lib.oracle_einsum_at, lib.oracle_einsum_grad,
+              lib.oracle_einsum_grad_at):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -155,6 +159,25 @@ def einsum_grad(notation: str, arrays, G, wrt: int) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle rejected notation {notation!r}")
     return dA
+
+
+def einsum_grad_at(notation: str, arrays, G, wrt: int, flat_positions) -> np.ndarray:
+    """Entries of d<G, R>/d arrays[wrt] at flat row-major positions of that
+    operand (its index letters must be distinct)."""
+    lib = _load()
+    ins, out, arrs, ndim, labels, outl, extc, ptrs, shape = _marshal(notation, arrays)
+    g = np.array(G, dtype=np.float64, order="C")
+    if g.shape != shape:
+        raise ValueError("G must have the output's shape")
+    where = np.ascontiguousarray(flat_positions, dtype=np.int64)
+    vals = np.empty(where.shape, dtype=np.float64)
+    rc = lib.oracle_einsum_grad_at(len(ins), ndim, labels, len(out), outl, extc, ptrs,
+                                   g.ctypes.data, wrt, where.size,
+                                   where.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                                   vals.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle rejected notation {notation!r} for wrt={wrt}")
+    return vals
 
 
 def batched_einsum(notation: str, table, arrays: dict):

@@ -151,6 +151,74 @@ int oracle_einsum_at(int n_ops, const int *ndim, const int *labels, int n_out,
   return 0;
 }
 
+/* Selected entries of the gradient below: for each flat row-major position
+ * of operand `wrt` (whose labels must be distinct), the sum over every other
+ * label of G[I_out] * prod_{m != wrt} A^m.  Used at sizes where the full
+ * gradient loop would take too long. */
+int oracle_einsum_grad_at(int n_ops, const int *ndim, const int *labels, int n_out,
+                          const int *out_labels, const i64 *extent,
+                          const double *const *ops, const double *G, int wrt,
+                          i64 n_where, const i64 *where, double *vals) {
+  if (n_ops < 1 || n_ops > MAXOPS || wrt < 0 || wrt >= n_ops) return -1;
+  int used[MAXL], in_out[MAXL];
+  if (classify(n_ops, ndim, labels, n_out, out_labels, used, in_out)) return -1;
+  i64 stride[MAXOPS][MAXL];
+  if (build_strides(n_ops, ndim, labels, extent, stride)) return -1;
+  int off = 0;
+  for (int k = 0; k < wrt; ++k) off += ndim[k];
+  const int *wl = labels + off;
+  int in_w[MAXL];
+  for (int l = 0; l < MAXL; ++l) in_w[l] = 0;
+  for (int d = 0; d < ndim[wrt]; ++d) {
+    if (in_w[wl[d]]) return -1; /* repeated label in the wrt operand */
+    in_w[wl[d]] = 1;
+  }
+  i64 gstride[MAXL];
+  for (int l = 0; l < MAXL; ++l) gstride[l] = 0;
+  {
+    i64 s = 1;
+    for (int d = n_out - 1; d >= 0; --d) {
+      gstride[out_labels[d]] = s;
+      s *= extent[out_labels[d]];
+    }
+  }
+  int rest[MAXL], n_rest = 0;
+  for (int l = 0; l < MAXL; ++l)
+    if (used[l] && !in_w[l]) rest[n_rest++] = l;
+  i64 n_terms = 1;
+  for (int a = 0; a < n_rest; ++a) n_terms *= extent[rest[a]];
+#pragma omp parallel for schedule(dynamic, 1)
+  for (i64 w = 0; w < n_where; ++w) {
+    i64 val[MAXL];
+    for (int l = 0; l < MAXL; ++l) val[l] = 0;
+    i64 rem = where[w];
+    for (int d = ndim[wrt] - 1; d >= 0; --d) {
+      val[wl[d]] = rem % extent[wl[d]];
+      rem /= extent[wl[d]];
+    }
+    double acc = 0.0;
+    for (i64 t = 0; t < n_terms; ++t) {
+      i64 r = t;
+      for (int a = n_rest - 1; a >= 0; --a) {
+        val[rest[a]] = r % extent[rest[a]];
+        r /= extent[rest[a]];
+      }
+      i64 go = 0;
+      for (int l = 0; l < MAXL; ++l) go += val[l] * gstride[l];
+      double prod = G[go];
+      for (int k = 0; k < n_ops; ++k) {
+        if (k == wrt) continue;
+        i64 o = 0;
+        for (int l = 0; l < MAXL; ++l) o += val[l] * stride[k][l];
+        prod *= ops[k][o];
+      }
+      acc += prod;
+    }
+    vals[w] = acc;
+  }
+  return 0;
+}
+
 /* Gradient of sum(G * R) with respect to operand `wrt`, by the definition of
  * the derivative of a multilinear form: for every assignment of all indices,
  *   dA_wrt[I^{in,wrt}] += G[I_out] * prod_{m != wrt} A^m[I^{in,m}].

@@ -18,14 +18,20 @@ UNARY_OPS = ("id", "sin", "cos", "square")
 
 def strided_view(flat_source, shape, strides, offset=0) -> np.ndarray:
     """M(A)[i_1..i_d] = S[offset + sum_k i_k * strides[k]] (element strides)."""
-    src = np.asarray(flat_source, dtype=np.float64).reshape(-1)
+    src = np.ascontiguousarray(np.asarray(flat_source, dtype=np.float64).reshape(-1))
     if len(shape) == 0:
         return np.array(src[offset])
-    grids = np.indices(tuple(shape), dtype=np.int64)
-    pos = np.full(tuple(shape), offset, dtype=np.int64)
-    for k, s in enumerate(strides):
-        pos = pos + grids[k] * int(s)
-    return src[pos]
+    lo = offset + sum(min(0, (n - 1) * s) for n, s in zip(shape, strides))
+    hi = offset + sum(max(0, (n - 1) * s) for n, s in zip(shape, strides))
+    if any(n == 0 for n in shape):
+        return np.zeros(tuple(shape))
+    if lo < 0 or hi >= src.size:
+        raise IndexError("view reaches outside its source")
+    item = src.itemsize
+    view = np.lib.stride_tricks.as_strided(src[offset:], shape=tuple(shape),
+                                           strides=tuple(int(s) * item for s in strides),
+                                           writeable=False)
+    return np.array(view)
 
 
 def unary(x, op: str) -> np.ndarray:

@@ -87,12 +87,18 @@ bool env_flag(const char *name) {
   return s && *s && std::strcmp(s, "0") != 0;
 }
 
-hipError_t ensure_generic_dev(const bes::Plan &p, const GenEinsum &g) {
+// Device copy of the plan's generic descriptor for config `cfg`; re-uploaded
+// only when the config or the device changes (after draining the device, so
+// no launch in flight still reads the old copy).
+hipError_t ensure_generic_dev(const bes::Plan &p, const GenEinsum &g, const bes_config &cfg) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  bool same_cfg = std::memcmp(&p.gen_dev_cfg, &p.cfg, sizeof p.cfg) == 0;
+  bool same_cfg = std::memcmp(&p.gen_dev_cfg, &cfg, sizeof cfg) == 0;
   if (p.gen_dev && p.gen_dev_device == dev && same_cfg) return hipSuccess;
+  if (p.gen_dev) {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+  }
   if (p.gen_dev && p.gen_dev_device != dev) {
     (void)hipFree(p.gen_dev);
     p.gen_dev = nullptr;
@@ -107,7 +113,7 @@ hipError_t ensure_generic_dev(const bes::Plan &p, const GenEinsum &g) {
   e = hipMemcpy(p.gen_dev, &g, sizeof g, hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   p.gen_dev_device = dev;
-  p.gen_dev_cfg = p.cfg;
+  p.gen_dev_cfg = cfg;
   return hipSuccess;
 }
 
@@ -162,6 +168,7 @@ int bes_register(bes_ctx *ctx, const char *notation, int32_t b, int32_t n, int32
 void bes_plan_destroy(bes_plan *plan) {
   if (!plan) return;
   if (plan->p.gen_dev) (void)hipFree(plan->p.gen_dev);
+  if (plan->p.fem_ws) (void)hipFree(plan->p.fem_ws);
   delete plan;
 }
 
@@ -283,7 +290,21 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
       FemArgs a;
       int rc = bes::bind_fem(p, src.data(), out_ptrs, a, err);
       if (rc) return fail(rc, err);
-      e = bes::launch_fem(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, a, p.cfg.p[0], p.cfg.p[1],
+      int dev = 0;
+      if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+      if (p.fem_ws && p.fem_ws_device != dev) {
+        (void)hipFree(p.fem_ws);
+        p.fem_ws = nullptr;
+      }
+      if (!p.fem_ws) {
+        size_t bytes = bes::fem_workspace_bytes(f64, p.fem.NI, p.fem.NJ, p.fem.NR);
+        if ((e = hipMalloc(&p.fem_ws, bytes)) != hipSuccess) {
+          p.fem_ws = nullptr;
+          return hip_fail(e, "FEM workspace allocation");
+        }
+        p.fem_ws_device = dev;
+      }
+      e = bes::launch_fem(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, a, p.fem_ws, p.cfg.p[1],
                           stream);
       if (e != hipSuccess) return hip_fail(e, "FEM-stream launch");
       return BES_OK;
@@ -293,18 +314,28 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
       int rc = bes::bind_mfma(p, src.data(), out_ptrs, a, err);
       if (rc) return fail(rc, err);
       e = bes::launch_mfma(a, p.cfg.p[0], p.cfg.p[1], stream);
-      if (e != hipSuccess) return hip_fail(e, "MFMA launch");
-      return BES_OK;
+      if (e == hipSuccess) return BES_OK;
+      if (e != hipErrorInvalidValue) return hip_fail(e, "MFMA launch");
+      // unaligned rows for the vector tile loads: evaluate with the generic
+      // template instead
+      [[fallthrough]];
     }
     case BES_T_GENERIC: {
+      bes_config gc = p.cfg;
+      if (gc.template_id != BES_T_GENERIC) {  // fallback from another template
+        gc = bes_config{};
+        gc.template_id = BES_T_GENERIC;
+        gc.p[0] = 256;
+        gc.p[1] = 1;
+      }
       GenEinsum *g = new (std::nothrow) GenEinsum;
       if (!g) return fail(BES_E_NOMEM, "out of host memory");
-      int rc = bes::bind_generic_static(p, p.cfg, *g, err);
+      int rc = bes::bind_generic_static(p, gc, *g, err);
       if (rc) {
         delete g;
         return fail(rc, err);
       }
-      e = ensure_generic_dev(p, *g);
+      e = ensure_generic_dev(p, *g, gc);
       if (e != hipSuccess) {
         delete g;
         return hip_fail(e, "generic descriptor upload");

@@ -42,9 +42,18 @@ typedef struct FemMember {
 } FemMember;
 
 typedef struct FemGroup {
-  const void *S;    // dense [NR][NI][NJ] in role order
+  const void *S;    // the caller's S (offset applied)
+  int64_t ss[3];    // S strides along (r, i, j); the launcher packs S once per
+                    // launch into [r][j][i] for the kernel
   FemSrc u;
   int32_t m0, m1;   // members [m0, m1) use this group
+  int32_t g_row;    // > 0: the G operands of all members of the group read
+                    // one row of g_row (<= 12) contiguous components per
+                    // element, p0 + g_off + e * s0[0] + c, from one source
+                    // (views of one buffer, or dense tetrahedron vertex rows);
+                    // the row is staged once per tile and shared
+  int32_t pad;
+  int64_t g_off;
 } FemGroup;
 
 typedef struct FemArgs {

@@ -15,8 +15,9 @@
 
 namespace bes {
 
-// The MFMA template is selected by default only once its kernel is built.
-constexpr bool kMfmaTemplateReady = false;
+// The MFMA template is selected by default (128 x 128 output tiles, K in
+// steps of 16).
+constexpr bool kMfmaTemplateReady = true;
 
 namespace {
 
@@ -166,21 +167,30 @@ void analyse_fem(Plan &p) {
   R.NX = R.x >= 0 ? (int)e.extent[R.x] : 1;
   if (!fem_shape_compiled(p.spec.dtype == BES_FLOAT64, R.NI, R.NJ, R.NR, R.NX))
     return fail("no compiled instantiation for these extents");
-  // Operand kinds and the dense role-order layout of S.
+  // Operand kinds (S may have any strides: the launcher packs it).
   for (int k = 0; k < e.b; ++k) {
     const Operand &s = p.spec.args[slot_arg(p, k, R.posS)];
     if (s.kind != BES_ARRAY && s.kind != BES_VIEW) return fail("S must be an array or view");
-    int64_t sr = R.r >= 0 ? stride_of(p, slot_arg(p, k, R.posS), R.posS, 0, R.r) : 0;
-    int64_t si = stride_of(p, slot_arg(p, k, R.posS), R.posS, 0, R.i);
-    int64_t sj = stride_of(p, slot_arg(p, k, R.posS), R.posS, 0, R.j);
-    if (sj != 1 || si != R.NJ || (R.r >= 0 && sr != (int64_t)R.NI * R.NJ))
-      return fail("S is not dense in (r, i, j) order");
     const Operand &u = p.spec.args[slot_arg(p, k, R.posU)];
     if (u.kind == BES_TET_JACOBIAN) return fail("U cannot be a Jacobian operand");
     if (R.posG >= 0) {
       const Operand &g = p.spec.args[slot_arg(p, k, R.posG)];
       if (g.kind == BES_TET_JACOBIAN && (R.NX != 3 || R.NR != 3))
         return fail("Jacobian operand needs x = r = 3");
+    }
+    // The kernel addresses a 64-element tile with 32-bit element offsets.
+    for (int pos : {R.posU, R.posG}) {
+      if (pos < 0) continue;
+      const Operand &o = p.spec.args[slot_arg(p, k, pos)];
+      for (int s = 0; s < o.nsrc; ++s) {
+        int64_t span = 0;
+        for (int d = 0; d < o.ndim; ++d) {
+          int64_t st = o.src_strides[s][d] < 0 ? -o.src_strides[s][d] : o.src_strides[s][d];
+          int64_t ext = (o.kind == BES_TET_JACOBIAN) ? 4 : o.shape[d];
+          span += (d == 0 ? 64 : ext) * st;
+        }
+        if (span >= ((int64_t)1 << 31)) return fail("per-tile offsets exceed 32 bits");
+      }
     }
   }
   p.fem = R;
@@ -260,8 +270,8 @@ void analyse_mfma(Plan &p) {
   for (int c : R.Mi) R.M *= e.extent[c];
   for (int c : R.Ni) R.N *= e.extent[c];
   for (int c : R.Ki) R.K *= e.extent[c];
-  if (R.M % 64 || R.N % 64 || R.K % 16 || R.M < 64 || R.N < 64)
-    return fail("M, N not multiples of 64 or K of 16");
+  if (R.M % 128 || R.N % 128 || R.K % 16)
+    return fail("M, N not multiples of 128 or K of 16");
   int64_t st;
   for (int k = 0; k < e.b; ++k) {
     int a = slot_arg(p, k, R.posA), b = slot_arg(p, k, R.posB);
@@ -303,8 +313,8 @@ bes_config default_config(const Plan &p) {
     c.p[1] = 128;
   } else if (p.fem_ok) {
     c.template_id = BES_T_FEM_STREAM;
-    c.p[0] = 256;
-    c.p[1] = 4;
+    c.p[0] = 64;   // elements per tile (one wave)
+    c.p[1] = 8;    // resident one-wave blocks per CU
   } else if (template_supported(p, BES_T_GENERIC)) {
     c.template_id = BES_T_GENERIC;
     c.p[0] = 256;
@@ -421,6 +431,9 @@ int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a
     G.S = src[p.src_base[keys[g].first]];
     const Operand &so = p.spec.args[keys[g].first];
     G.S = (const char *)G.S + so.src_offset[0] * (p.spec.dtype == BES_FLOAT64 ? 8 : 4);
+    G.ss[0] = R.r >= 0 ? stride_of(p, keys[g].first, R.posS, 0, R.r) : 0;
+    G.ss[1] = stride_of(p, keys[g].first, R.posS, 0, R.i);
+    G.ss[2] = stride_of(p, keys[g].first, R.posS, 0, R.j);
     int k0 = -1;
     for (int k = 0; k < e.b; ++k)
       if (group_of[k] == g) {
@@ -447,6 +460,35 @@ int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a
     }
     G.m1 = m;
     (void)k0;
+    // Shared G row: all members read one contiguous row of <= 12 components
+    // per element from the same source.
+    G.g_row = 0;
+    G.g_off = 0;
+    if (R.posG >= 0 && G.m1 > G.m0) {
+      const FemSrc &f0 = a.mem[G.m0].g;
+      bool same = true, views = f0.kind == FEM_SRC_ARRAY, tets = f0.kind == FEM_SRC_TET;
+      int64_t hi = -1;
+      for (int q = G.m0; q < G.m1 && same; ++q) {
+        const FemSrc &f = a.mem[q].g;
+        same = f.p0 == f0.p0 && f.s0[0] == f0.s0[0] && f.kind == f0.kind;
+        if (views) {
+          for (int x = 0; x < R.NX && same; ++x)
+            for (int r = 0; r < R.NR; ++r) {
+              int64_t c = f.off0 + x * f.s0[1] + r * f.s0[2];
+              if (c < 0 || c >= 12) same = false;
+              hi = std::max(hi, c);
+            }
+        } else if (tets) {
+          same = same && f.off0 == f0.off0 && f.s0[1] == 3 && f.s0[2] == 1;
+        } else {
+          same = false;
+        }
+      }
+      if (same && f0.s0[0] > 0 && f0.s0[0] < (1 << 24)) {
+        G.g_row = views ? (int32_t)(hi + 1) : 12;
+        G.g_off = views ? 0 : f0.off0;
+      }
+    }
   }
   return BES_OK;
 }

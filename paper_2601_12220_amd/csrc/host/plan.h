@@ -54,6 +54,9 @@ struct Plan {
   std::vector<int> src_from;
   bool adjoint = false;
 
+  // FEM-stream workspace for the packed shared operand (first FEM launch).
+  mutable void *fem_ws = nullptr;
+  mutable int fem_ws_device = -1;
   // Device copy of the generic descriptor (created on first generic launch).
   mutable void *gen_dev = nullptr;
   mutable int gen_dev_device = -1;

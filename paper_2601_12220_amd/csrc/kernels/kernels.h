@@ -11,9 +11,11 @@ namespace bes {
 // Compute units of the current device (cached per device).
 int device_cu_count();
 
-// FEM-stream template.  `block` threads per block, `blocks_per_cu` resident
-// blocks per compute unit for the grid-stride loop.
-hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, int block,
+// FEM-stream template: a pack of S into `workspace` (at least
+// fem_workspace_bytes) followed by the stream kernel with `blocks_per_cu`
+// one-wave blocks per compute unit walking 64-element tiles.
+size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR);
+hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
                       int blocks_per_cu, hipStream_t stream);
 
 // Generic template: one launch over (slot, tile) pairs.  `dev` is the device

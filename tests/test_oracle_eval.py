@@ -164,3 +164,18 @@ def test_grad_central_differences(notation, shapes):
             fd[idx] = (np.sum(G * oracle.einsum(notation, *p)) -
                        np.sum(G * oracle.einsum(notation, *m))) / (2 * h)
         np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("notation,shapes", [
+    ("abij,cdab->cdij", [(2, 3, 2, 2), (3, 2, 2, 3)]),
+    ("er,rij,ej->ei", [(5, 3), (3, 4, 4), (5, 4)]),
+])
+def test_grad_at_matches_full_grad(notation, shapes):
+    ops = [_rand(*s) for s in shapes]
+    R = oracle.einsum(notation, *ops)
+    G = _rand(*R.shape)
+    for k in range(len(ops)):
+        full = oracle.einsum_grad(notation, ops, G, k)
+        pos = np.arange(full.size)
+        np.testing.assert_allclose(oracle.einsum_grad_at(notation, ops, G, k, pos),
+                                   full.ravel(), rtol=1e-13, atol=1e-13)
