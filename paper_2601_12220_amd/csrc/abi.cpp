@@ -305,7 +305,7 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
         p.fem_ws_device = dev;
       }
       e = bes::launch_fem(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, a, p.fem_ws, p.cfg.p[1],
-                          stream);
+                          p.cfg.p[2] != 0, stream);
       if (e != hipSuccess) return hip_fail(e, "FEM-stream launch");
       return BES_OK;
     }

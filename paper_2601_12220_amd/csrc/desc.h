@@ -38,7 +38,7 @@ typedef struct FemMember {
   void *out;
   int64_t oe, ox, oi;  // output strides along (e, x, i)
   int32_t group;
-  int32_t pad;
+  int32_t o_dense;     // set by the launcher: oe == NX*NI, ox == NI, oi == 1
 } FemMember;
 
 typedef struct FemGroup {
@@ -52,13 +52,17 @@ typedef struct FemGroup {
                     // element, p0 + g_off + e * s0[0] + c, from one source
                     // (views of one buffer, or dense tetrahedron vertex rows);
                     // the row is staged once per tile and shared
-  int32_t pad;
+  int32_t u_dense;  // set by the launcher: U's source rows are dense
+                    // (s0 = (NJ, 1), and s1 likewise for a second source)
   int64_t g_off;
 } FemGroup;
 
 typedef struct FemArgs {
   int64_t E;                 // number of stream elements
   int32_t n_groups, n_members;
+  int32_t g_same;            // every member reads the same G through one shared
+                             // row: the row is staged once per tile
+  int32_t pad;
   FemGroup grp[BES_FEM_MAX_GROUPS];
   FemMember mem[BES_FEM_MAX_MEMBERS];
 } FemArgs;

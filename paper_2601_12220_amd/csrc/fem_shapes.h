@@ -5,10 +5,12 @@
 // and plain element-wise mat-vecs (r and x absent).
 #pragma once
 
+#ifndef BES_FEM_SHAPES
 #define BES_FEM_SHAPES(X)                                                  \
   X(4, 4, 1, 1) X(10, 10, 1, 1) X(20, 20, 1, 1) X(35, 35, 1, 1)            \
   X(4, 4, 3, 1) X(10, 10, 3, 1) X(20, 20, 3, 1) X(35, 35, 3, 1)            \
   X(4, 4, 3, 3) X(10, 10, 3, 3) X(20, 20, 3, 3) X(35, 35, 3, 3)
+#endif
 
 inline bool fem_shape_compiled(bool /*f64*/, int ni, int nj, int nr, int nx) {
 #define BES_FEM_MATCH(a, b, c, d) \

@@ -11,22 +11,29 @@
 // DG-FEM transformations use to cut FLOPs; members whose S and U are the same
 // arguments share T (the operand reuse that motivates batching).
 //
-// Mapping (one wave per block, a tile of 64 consecutive elements per wave,
-// one element per lane):
-//   * staging: every per-element source is read with coalesced loads (lane k
-//     reads flat position k, k+64, ... of the tile's rows) and written to LDS
-//     transposed, [component][lane] with an odd pitch, so each lane then reads
-//     its own element's components without bank conflicts.  Element-wise
-//     functional operands (alpha*op(S0)+beta+S1) are evaluated during that
-//     coalesced pass, in registers; the tetrahedron Jacobian is formed from
-//     the staged vertex row;
-//   * stage 1 runs j-outer over S packed as [r][j][i]: S is wave-uniform, so
-//     it lives in scalar registers (contiguous s_load) and is the scalar
-//     operand of every v_fma; T[r][i] stays in vector registers;
-//   * stage 2 writes each (member, x) output row for the 64 elements to LDS
-//     and then to HBM as one contiguous run per element (consecutive lanes,
-//     consecutive addresses).
+// Mapping: one wave per block, a tile of 64 consecutive elements per wave,
+// one element per lane.  Occupancy, not arithmetic, decides the speed of this
+// HBM-bound stream, so every choice below keeps the per-wave footprint small:
+//   * one LDS staging region X of max(NJ, 12, IC) rows x 65 (odd pitch) per
+//     wave, reused in turn for the G row, the U rows and the output rows;
+//   * per-element sources are read with coalesced loads (lane k reads flat
+//     position k, k+64, ... of the tile's rows); the G loads and the U loads
+//     of a tile are issued together so their HBM latencies overlap, and with
+//     PF the raw loads of the next tile are issued before the current tile's
+//     arithmetic (register double buffering);
+//   * element-wise functional operands (alpha*op(S0)+beta+S1) are evaluated
+//     in registers during the coalesced pass; the tetrahedron Jacobian is
+//     formed from the staged vertex row, once per tile when every member
+//     reads the same one;
+//   * stage 1 runs over i-chunks of IC outputs: T[r][0..IC) lives in
+//     registers, S is packed [r][j][i] so a chunk row S[r][j][i0..i0+IC) is a
+//     contiguous wave-uniform run (scalar loads, scalar FMA operand);
+//     u comes from LDS (IC == NI) or from registers (UREG, several chunks);
+//   * stage 2 writes each (member, x, chunk) block to X and then to HBM as
+//     runs of IC contiguous values per element.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "../fem_shapes.h"
 #include "kernels.h"
@@ -39,6 +46,7 @@ namespace {
 constexpr int kTile = 64;      // elements per wave tile = lanes per wave
 constexpr int kPitch = kTile + 1;
 constexpr int kMaxRow = 12;    // staged G row width (TET: 4 x 3 vertex coords)
+constexpr int kGW = 4;         // i-group width of the S layout used with u in registers
 
 template <typename T>
 __device__ __forceinline__ T apply_op(int op, T v) {
@@ -50,74 +58,70 @@ __device__ __forceinline__ T apply_op(int op, T v) {
   }
 }
 
-// Out-of-line element-wise function: keeps the transcendental expansions from
-// being interleaved across a whole unrolled row (register pressure).
+// Element-wise functional operand value alpha * op(v) + beta + w (inline: a
+// call would make the caller save its live registers to scratch).
 template <typename T>
-__device__ __noinline__ T elementwise_call(int op, T v, T alpha, T beta, T w) {
+__device__ __forceinline__ T elementwise_call(int op, T v, T alpha, T beta, T w) {
   return alpha * apply_op<T>(op, v) + beta + w;
 }
 
-// Stage `W` components of every element of the tile [e0, e0 + n) into
-// lds[c * kPitch + el].  Component c of element e sits at
-//   p0[off0 + e * s0e + pos0(c)]  (and p1[off1 + e * s1e + pos1(c)])
-// where pos(c) = (c / div) * sa + (c % div) * sb.  Loads walk the flat index
-// f = el * W + c with consecutive lanes on consecutive f (coalesced when the
-// rows are dense).  Element-wise prologues are applied here.
-// In-tile offsets are 32-bit element counts from a wave-uniform base pointer
-// (the planner guarantees they fit), so each load needs one address VGPR.
+// Position of component c (of W) of element el in a source whose element
+// stride is se and whose component c = ca * DIV + cb sits at ca*sa + cb*sb.
+template <int W, int DIV>
+__device__ __forceinline__ int src_pos(int f, int se, int sa, int sb, int &el, int &c) {
+  el = f / W;
+  c = f - el * W;
+  const int ca = c / DIV, cb = c - ca * DIV;
+  return el * se + ca * sa + cb * sb;
+}
+
+// Raw coalesced loads of W components for the 64 elements of a full tile:
+// v[k] holds flat position lane + 64 k of the tile's (element, component)
+// block.  In-tile offsets are 32-bit element counts from a wave-uniform base
+// (the planner guarantees they fit).
+template <typename T, int W, int DIV>
+__device__ __forceinline__ void load_rows(T (&v)[W], const T *__restrict__ p, int se, int sa,
+                                          int sb, int lane) {
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    int el, c;
+    v[k] = p[src_pos<W, DIV>(lane + kTile * k, se, sa, sb, el, c)];
+  }
+}
+
+// Write raw loads (full tile) into X as [component][element].
+template <typename T, int W>
+__device__ __forceinline__ void put_rows(T *__restrict__ X, const T (&v)[W], int lane) {
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const int f = lane + kTile * k;
+    const int el = f / W, c = f - el * W;
+    X[c * kPitch + el] = v[k];
+  }
+}
+
+// Partial tile (n < 64 elements) or a source that needs two buffers: rolled
+// loop with the element-wise prologue applied per value.
 template <typename T, int W, int DIV, bool EW>
-__device__ __forceinline__ void stage_rows(T *__restrict__ lds, const FemSrc &s, int64_t sa0,
-                                           int64_t sb0, int64_t sa1, int64_t sb1, int64_t e0,
-                                           int n, int lane) {
+__device__ __forceinline__ void stage_rows_rolled(T *__restrict__ X, const FemSrc &s, int64_t e0,
+                                                  int n, int lane) {
   const T *__restrict__ p0 = (const T *)s.p0 + s.off0 + e0 * s.s0[0];
-  const int se0 = (int)s.s0[0], a0 = (int)sa0, b0 = (int)sb0;
+  const int se0 = (int)s.s0[0], a0 = (int)s.s0[1], b0 = (int)s.s0[2];
   const bool ew = EW && s.kind == FEM_SRC_ELEMENTWISE;
   const bool two = ew && s.p1 != nullptr;
   const T *__restrict__ p1 = two ? (const T *)s.p1 + s.off1 + e0 * s.s1[0] : p0;
-  const int se1 = (int)s.s1[0], a1 = (int)sa1, b1 = (int)sb1;
-  const T alpha = (T)s.alpha, beta = (T)s.beta;
-  if (n == kTile) {
-    // Full tile: W loads per lane, all issued before any is consumed so their
-    // HBM latencies overlap; the prologue and the LDS writes follow.
-    T v[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      const int f = lane + kTile * k;
-      const int el = f / W, c = f - el * W;
-      const int ca = c / DIV, cb = c - ca * DIV;
-      v[k] = p0[el * se0 + ca * a0 + cb * b0];
-    }
-    if (ew) {
-      T w[W];
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        const int f = lane + kTile * k;
-        const int el = f / W, c = f - el * W;
-        const int ca = c / DIV, cb = c - ca * DIV;
-        w[k] = two ? p1[el * se1 + ca * a1 + cb * b1] : (T)0;
-      }
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        if constexpr (EW) v[k] = elementwise_call<T>(s.op, v[k], alpha, beta, w[k]);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      const int f = lane + kTile * k;
-      const int el = f / W, c = f - el * W;
-      lds[c * kPitch + el] = v[k];
-    }
-    return;
-  }
-  const int total = n * W;
-  for (int f = lane; f < total; f += kTile) {
-    const int el = f / W, c = f - el * W;
-    const int ca = c / DIV, cb = c - ca * DIV;
-    T v = p0[el * se0 + ca * a0 + cb * b0];
+  const int se1 = (int)s.s1[0], a1 = (int)s.s1[1], b1 = (int)s.s1[2];
+  for (int f = lane; f < n * W; f += kTile) {
+    int el, c;
+    T v = p0[src_pos<W, DIV>(f, se0, a0, b0, el, c)];
     if constexpr (EW) {
-      if (ew) v = elementwise_call<T>(s.op, v, alpha, beta, two ? p1[el * se1 + ca * a1 + cb * b1] : (T)0);
+      if (ew) {
+        T w = (T)0;
+        if (two) w = p1[src_pos<W, DIV>(f, se1, a1, b1, el, c)];
+        v = elementwise_call<T>(s.op, v, (T)s.alpha, (T)s.beta, w);
+      }
     }
-    lds[c * kPitch + el] = v;
+    X[c * kPitch + el] = v;
   }
 }
 
@@ -125,13 +129,13 @@ __device__ __forceinline__ void stage_rows(T *__restrict__ lds, const FemSrc &s,
 // (components vertex * 3 + coordinate): J[x][r] = V[r+1][x] - V[0][x]; the
 // kernel's (x, r) may be the operand's (r, x).  NX = NR = 3 on this path.
 template <typename T, int NX, int NR>
-__device__ __forceinline__ void tet_from_lds(const T *__restrict__ lds, int lane, bool swapped,
+__device__ __forceinline__ void tet_from_lds(const T *__restrict__ X, int lane, bool swapped,
                                              T (&g)[NX][NR]) {
   T v[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[k][c] = lds[(k * 3 + c) * kPitch + lane];
+    for (int c = 0; c < 3; ++c) v[k][c] = X[(k * 3 + c) * kPitch + lane];
 #pragma unroll
   for (int x = 0; x < NX; ++x)
 #pragma unroll
@@ -142,221 +146,450 @@ __device__ __forceinline__ void tet_from_lds(const T *__restrict__ lds, int lane
     }
 }
 
-// Kernels that may meet tetrahedron-Jacobian G operands: x = r = 3 and one
-// member per group (the launcher keeps such groups at one member).
-template <int NX, int NR, int MPG>
-constexpr bool kTetCapable = NX == 3 && NR == 3 && MPG == 1;
+template <int NX, int NR>
+constexpr bool kTetCapable = NX == 3 && NR == 3;
 
-// G_m[e, x, r] of every member of the group into registers.
-//   Shared row (G.g_row > 0): one coalesced, fully unrolled pass stages the
-//   row p0 + g_off + e * se + c, c < g_row, for the 64 elements; each member
-//   then reads its components (views: offset off0 + x*sx + r*sr in the row;
-//   tetrahedra: the 12 vertex coordinates).
-//   Otherwise each member's components are staged in turn (rolled loop).
-template <typename T, int NX, int NR, int MPG, bool EW>
-__device__ __forceinline__ void load_group_g(T *__restrict__ lds, const FemArgs &a,
-                                             const FemGroup &G, int m0, int nm, int64_t e0, int n,
-                                             int lane, T (&gm)[MPG][NX][NR]) {
-  if (G.g_row > 0) {
-    const FemSrc &s0 = a.mem[m0].g;
-    const T *__restrict__ pb = (const T *)s0.p0 + G.g_off + e0 * s0.s0[0];
-    const int se = (int)s0.s0[0], row = G.g_row;
-    if (n == kTile) {
-      T v[kMaxRow];
+// G components of member descriptor s from the staged row in X:
+// views read (off0 + x*sx + r*sr) of the row, tetrahedra the 12 vertex
+// coordinates.
+template <typename T, int NX, int NR>
+__device__ __forceinline__ void g_from_row(const T *__restrict__ X, const FemSrc &s, int lane,
+                                           T (&g)[NX][NR]) {
+  if (kTetCapable<NX, NR> && s.kind == FEM_SRC_TET) {
+    if constexpr (kTetCapable<NX, NR>) tet_from_lds<T, NX, NR>(X, lane, s.s1[0] != 0, g);
+  } else {
+    const int off = (int)s.off0, sx = (int)s.s0[1], sr = (int)s.s0[2];
 #pragma unroll
-      for (int k = 0; k < kMaxRow; ++k) {
-        const int f = lane + kTile * k;
-        const int el = f / kMaxRow, c = f - el * kMaxRow;
-        v[k] = c < row ? pb[el * se + c] : (T)0;
-      }
+    for (int x = 0; x < NX; ++x)
 #pragma unroll
-      for (int k = 0; k < kMaxRow; ++k) {
-        const int f = lane + kTile * k;
-        const int el = f / kMaxRow, c = f - el * kMaxRow;
-        lds[c * kPitch + el] = v[k];
-      }
-    } else {
-      for (int f = lane; f < n * row; f += kTile) {
-        const int el = f / row, c = f - el * row;
-        lds[c * kPitch + el] = pb[el * se + c];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < MPG; ++q) {
-      if (q >= nm) break;
-      const FemSrc &s = a.mem[m0 + q].g;
-      if (kTetCapable<NX, NR, MPG> && s.kind == FEM_SRC_TET) {
-        if constexpr (kTetCapable<NX, NR, MPG>) tet_from_lds<T, NX, NR>(lds, lane, s.s1[0] != 0, gm[q]);
-      } else {
-        const int off = (int)s.off0, sx = (int)s.s0[1], sr = (int)s.s0[2];
-#pragma unroll
-        for (int x = 0; x < NX; ++x)
-#pragma unroll
-          for (int r = 0; r < NR; ++r) gm[q][x][r] = lds[(off + x * sx + r * sr) * kPitch + lane];
-      }
-    }
-    __syncthreads();
-    return;
-  }
-  for (int q = 0; q < nm && q < MPG; ++q) {
-    const FemSrc &s = a.mem[m0 + q].g;
-    const bool tet = s.kind == FEM_SRC_TET;
-    const int W = tet ? 12 : NX * NR;
-    const int div = tet ? 3 : NR;
-    const int64_t sa = s.s0[1], sb = s.s0[2];
-    const T *__restrict__ p0 = (const T *)s.p0 + s.off0 + e0 * s.s0[0];
-    const T *__restrict__ p1 =
-        s.p1 ? (const T *)s.p1 + s.off1 + e0 * s.s1[0] : nullptr;
-    for (int f = lane; f < n * W; f += kTile) {
-      const int el = f / W, c = f - el * W;
-      const int ca = c / div, cb = c - ca * div;
-      T v = p0[el * s.s0[0] + ca * sa + cb * sb];
-      if constexpr (EW) {
-        if (s.kind == FEM_SRC_ELEMENTWISE)
-          v = elementwise_call<T>(s.op, v, (T)s.alpha, (T)s.beta,
-                                  p1 ? p1[el * s.s1[0] + ca * s.s1[1] + cb * s.s1[2]] : (T)0);
-      }
-      lds[c * kPitch + el] = v;
-    }
-    __syncthreads();
-    // Every member is read with static indices in the q-unrolled loop below.
-#pragma unroll
-    for (int qq = 0; qq < MPG; ++qq) {
-      if (qq != q) continue;
-      if (kTetCapable<NX, NR, MPG> && tet) {
-        if constexpr (kTetCapable<NX, NR, MPG>) tet_from_lds<T, NX, NR>(lds, lane, s.s1[0] != 0, gm[qq]);
-      } else {
-#pragma unroll
-        for (int x = 0; x < NX; ++x)
-#pragma unroll
-          for (int r = 0; r < NR; ++r) gm[qq][x][r] = lds[(x * NR + r) * kPitch + lane];
-      }
-    }
-    __syncthreads();
+      for (int r = 0; r < NR; ++r) g[x][r] = X[(off + x * sx + r * sr) * kPitch + lane];
   }
 }
 
-template <typename T, int NI, int NJ, int NR, int NX, int MPG, bool EW>
-__global__ void __launch_bounds__(kTile) fem_stream_kernel(const FemArgs a,
-                                                           const T *__restrict__ Spack) {
-  constexpr int kRowsU = NJ > NI ? NJ : NI;
-  __shared__ T lds_u[kRowsU * kPitch];   // U staging, then output staging
-  __shared__ T lds_g[kMaxRow * kPitch];  // G staging
-  const int lane = threadIdx.x;
+struct Unit {
+  int64_t tile;
+  int g;
+};
+
+// A fresh copy of the lane id that the compiler cannot see through: address
+// arithmetic derived from it is recomputed per work unit instead of being
+// hoisted out of the tile loop and held in VGPRs for the whole kernel (which
+// would cap occupancy at one wave per SIMD).
+__device__ __forceinline__ int fresh_lane() {
+  int l = (int)threadIdx.x;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
+// Coalesced raw loads of W components of the 64 elements of a full tile:
+// v[k] = component c of element el for the flat position f = lane + 64 k,
+// el = f / W, c = f % W; components c >= w are not loaded.
+//   dense: the tile's block is contiguous (element stride W, unit component
+//   stride): base + f, immediate offsets.
+template <typename T, int W>
+__device__ __forceinline__ void load_block(T (&v)[W], const T *__restrict__ p, bool dense, int se,
+                                           int sc, int w, int lane) {
+  if (dense) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[k] = p[lane + kTile * k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int f = lane + kTile * k;
+      const int el = f / W, c = f - el * W;
+      v[k] = c < w ? p[el * se + c * sc] : (T)0;
+    }
+  }
+}
+
+// Raw loads of a full tile into X as [component][element] (components < w).
+template <typename T, int W>
+__device__ __forceinline__ void put_block(T *__restrict__ X, const T (&v)[W], int w, int lane) {
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const int f = lane + kTile * k;
+    const int el = f / W, c = f - el * W;
+    if (W == 0 || c < w) X[c * kPitch + el] = v[k];
+  }
+}
+
+template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool PF,
+          bool UREG>
+struct Fem {
+  static constexpr int kRows = (NJ > kMaxRow ? (NJ > IC ? NJ : IC) : (kMaxRow > IC ? kMaxRow : IC));
+  static constexpr int kChunks = (NI + IC - 1) / IC;
+  static_assert(kChunks == 1 || UREG, "several i-chunks need u in registers");
+  static constexpr int kPfU = PF ? NJ : 1;
+  static constexpr int kPfG = PF ? kMaxRow : 1;
+};
+
+// Waves per SIMD the register allocation of an instantiation must allow
+// (the compiler otherwise spreads a kernel over VGPRs and AGPRs and ends at
+// one wave per SIMD): accumulators T[NR][IC], G of MPG members, u in
+// registers and the prefetch buffers, in 32-bit registers, plus a margin.
+template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool PF, bool UREG>
+constexpr int kWaves() {
+  constexpr int w = (int)sizeof(T) / 4;
+  constexpr int live = w * (NR * IC + MPG * NX * NR + (UREG ? NJ : 0) + (PF ? NJ + kMaxRow : 0)) + 40;
+  constexpr int waves = 512 / live;
+  return waves < 1 ? 1 : (waves > 8 ? 8 : waves);
+}
+
+template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool PF,
+          bool UREG>
+__global__ void __launch_bounds__(kTile)
+    __attribute__((amdgpu_waves_per_eu(kWaves<T, NI, NJ, NR, NX, MPG, IC, PF, UREG>())))
+    fem_stream_kernel(const FemArgs a, const T *__restrict__ Spack) {
+  using F = Fem<T, NI, NJ, NR, NX, MPG, IC, EW, PF, UREG>;
+  constexpr int kNG = F::kChunks * IC / kGW;   // i-groups (UREG layout)
+  static_assert(!UREG || IC % kGW == 0, "chunks must hold whole i-groups");
+  __shared__ T X[F::kRows * kPitch];
   const int64_t n_tiles = (a.E + kTile - 1) / kTile;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int64_t e0 = tile * kTile;
+  const int n_groups = a.n_groups;
+
+  // Shared-row width of a unit: g_same plans stage one row per tile (at the
+  // tile's first group), other plans one row per group.
+  auto row_of = [&](int g) -> int {
+    if (a.g_same) return g == 0 ? a.grp[0].g_row : 0;
+    return a.grp[g].g_row;
+  };
+  // Raw G-row and U loads of a unit (full tile, no element-wise U).
+  auto load_unit = [&](const Unit &w, int lane, T (&vu)[NJ], T (&vg)[kMaxRow]) {
+    const FemGroup &H = a.grp[w.g];
+    const int64_t f0 = w.tile * kTile;
+    const int hrow = a.mem[H.m0].g.kind != FEM_SRC_NONE ? row_of(w.g) : 0;
+    if (hrow > 0) {
+      const FemSrc &s0 = a.mem[H.m0].g;
+      const T *__restrict__ pb = (const T *)s0.p0 + H.g_off + f0 * s0.s0[0];
+      load_block<T, kMaxRow>(vg, pb, false, (int)s0.s0[0], 1, hrow, lane);
+    }
+    const T *__restrict__ pu0 = (const T *)H.u.p0 + H.u.off0 + f0 * H.u.s0[0];
+    load_block<T, NJ>(vu, pu0, H.u_dense != 0, (int)H.u.s0[0], (int)H.u.s0[1], NJ, lane);
+  };
+
+  // Prefetch registers (raw loads of the next unit, full tiles only).
+  T pu[F::kPfU];
+  T pg[F::kPfG];
+  bool have_pf = false;
+
+  T gm[MPG][NX][NR];   // G of the group's members (or of the plan, g_same)
+
+  Unit cur{(int64_t)blockIdx.x, 0};
+  while (cur.tile < n_tiles) {
+    const int lane = fresh_lane();
+    const int64_t e0 = cur.tile * kTile;
     const int n = (int)(a.E - e0 < kTile ? a.E - e0 : kTile);
-    for (int g = 0; g < a.n_groups; ++g) {
-      const FemGroup &G = a.grp[g];
-      const int m0 = G.m0, nm = G.m1 - G.m0;
-      const bool has_g = a.mem[m0].g.kind != FEM_SRC_NONE;
-      // G of every member of the group (registers).
-      T gm[MPG][NX][NR];
-      if (has_g) load_group_g<T, NX, NR, MPG, EW>(lds_g, a, G, m0, nm, e0, n, lane, gm);
-      // U rows of the tile, prologue applied, transposed into LDS.
-      stage_rows<T, NJ, NJ, EW>(lds_u, G.u, 0, G.u.s0[1], 0, G.u.s1[1], e0, n, lane);
-      __syncthreads();
-      // Stage 1: T[r][i] = sum_j S[r][j][i] u[j], S uniform (scalar operand).
-      T t[NR][NI];
+    const bool full = n == kTile;
+    const FemGroup &G = a.grp[cur.g];
+    const int m0 = G.m0, nm = G.m1 - G.m0;
+    const bool has_g = a.mem[m0].g.kind != FEM_SRC_NONE;
+    const int grow = has_g ? row_of(cur.g) : 0;
+    const bool g_each = has_g && G.g_row == 0 && !(a.g_same && cur.g > 0);
+    const bool u_ew = EW && G.u.kind == FEM_SRC_ELEMENTWISE;
+    const bool fast_u = full && !u_ew;
+
+    // ---- raw loads of this unit (unless prefetched) ------------------------
+    T ru[NJ];
+    T rg[kMaxRow];
+    if (have_pf) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
+      for (int k = 0; k < NJ; ++k) ru[k] = pu[PF ? k : 0];
 #pragma unroll
-        for (int i = 0; i < NI; ++i) t[r][i] = 0;
-      // r outer, j inner: one step needs the NI values S[r][j][:] (NI scalar
-      // register pairs), so the scalar file can hold the next step's S too.
-      const T *__restrict__ S = Spack + (int64_t)g * NR * NJ * NI;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-#pragma unroll 2
-        for (int j = 0; j < NJ; ++j) {
-          const T uj = lds_u[j * kPitch + lane];
-          const T *__restrict__ Srow = S + ((int64_t)r * NJ + j) * NI;
-#pragma unroll
-          for (int i = 0; i < NI; ++i) t[r][i] = fma(Srow[i], uj, t[r][i]);
+      for (int k = 0; k < kMaxRow; ++k) rg[k] = pg[PF ? k : 0];
+    } else if (full) {
+      if (fast_u) {
+        load_unit(cur, lane, ru, rg);
+      } else if (grow > 0) {
+        const FemSrc &s0 = a.mem[m0].g;
+        const T *__restrict__ pb = (const T *)s0.p0 + G.g_off + e0 * s0.s0[0];
+        load_block<T, kMaxRow>(rg, pb, false, (int)s0.s0[0], 1, grow, lane);
+      }
+    }
+
+    // ---- G to registers ---------------------------------------------------
+    if (grow > 0) {
+      if (full) {
+        put_block<T, kMaxRow>(X, rg, grow, lane);
+      } else {
+        const FemSrc &s0 = a.mem[m0].g;
+        const T *__restrict__ pb = (const T *)s0.p0 + G.g_off + e0 * s0.s0[0];
+        const int se = (int)s0.s0[0];
+        for (int f = lane; f < n * grow; f += kTile) {
+          const int el = f / grow, c = f - el * grow;
+          X[c * kPitch + el] = pb[el * se + c];
         }
       }
       __syncthreads();
-      // Stage 2 and contiguous stores, one (member, x) row block at a time.
+      if (a.g_same) {
+        g_from_row<T, NX, NR>(X, a.mem[0].g, lane, gm[0]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < MPG; ++q)
+          if (q < nm) g_from_row<T, NX, NR>(X, a.mem[m0 + q].g, lane, gm[q]);
+      }
+      __syncthreads();
+    } else if (g_each) {
+      for (int q = 0; q < nm && q < MPG; ++q) {
+        const FemSrc &s = a.mem[m0 + q].g;
+        const bool tet = s.kind == FEM_SRC_TET;
+        if (tet) {
+          stage_rows_rolled<T, 12, 3, false>(X, s, e0, n, lane);
+        } else {
+          stage_rows_rolled<T, NX * NR, NR, EW>(X, s, e0, n, lane);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int qq = 0; qq < MPG; ++qq) {
+          if (qq != q) continue;
+          if (kTetCapable<NX, NR> && tet) {
+            if constexpr (kTetCapable<NX, NR>) tet_from_lds<T, NX, NR>(X, lane, s.s1[0] != 0, gm[qq]);
+          } else {
+#pragma unroll
+            for (int x = 0; x < NX; ++x)
+#pragma unroll
+              for (int r = 0; r < NR; ++r) gm[qq][x][r] = X[(x * NR + r) * kPitch + lane];
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    // ---- U rows into X (prologue applied) ---------------------------------
+    if (fast_u) {
+      put_block<T, NJ>(X, ru, NJ, lane);
+    } else if (EW && u_ew && full && G.u_dense) {
+      // Element-wise U from dense sources: both raw loads coalesced, then
+      // alpha * op(S0) + beta (+ S1) per value in the coalesced mapping.
+      const T *__restrict__ p0 = (const T *)G.u.p0 + G.u.off0 + e0 * NJ;
+      load_block<T, NJ>(ru, p0, true, NJ, 1, NJ, lane);
+      T w[NJ];
+      if (G.u.p1) {
+        const T *__restrict__ p1 = (const T *)G.u.p1 + G.u.off1 + e0 * NJ;
+        load_block<T, NJ>(w, p1, true, NJ, 1, NJ, lane);
+      } else {
+#pragma unroll
+        for (int k = 0; k < NJ; ++k) w[k] = (T)0;
+      }
+      const T alpha = (T)G.u.alpha, beta = (T)G.u.beta;
+      const int op = G.u.op;
+#pragma unroll
+      for (int k = 0; k < NJ; ++k) ru[k] = alpha * apply_op<T>(op, ru[k]) + beta + w[k];
+      put_block<T, NJ>(X, ru, NJ, lane);
+    } else {
+      stage_rows_rolled<T, NJ, 1, EW>(X, G.u, e0, n, lane);  // U strides (e, j)
+    }
+    __syncthreads();
+
+    // ---- next unit and its prefetch -----------------------------------------
+    Unit nxt = cur;
+    if (++nxt.g >= n_groups) {
+      nxt.g = 0;
+      nxt.tile += gridDim.x;
+    }
+    have_pf = false;
+    if constexpr (PF) {
+      if (nxt.tile < n_tiles && (nxt.tile + 1) * kTile <= a.E &&
+          !(EW && a.grp[nxt.g].u.kind == FEM_SRC_ELEMENTWISE)) {
+        load_unit(nxt, lane, pu, pg);
+        have_pf = true;
+      }
+    }
+
+    // ---- u into registers (several chunks) ----------------------------------
+    T ur[UREG ? NJ : 1];
+    if constexpr (UREG) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) ur[j] = X[j * kPitch + lane];
+      __syncthreads();
+    }
+
+    const T *__restrict__ S = Spack + (int64_t)cur.g * NR * NJ * (UREG ? kNG * kGW : NI);
+    (void)kNG;
+    bool o_fast = full;
+#pragma unroll
+    for (int q = 0; q < MPG; ++q)
+      if (q < nm) o_fast = o_fast && a.mem[m0 + q].o_dense;
+    // Stage 2 and stores of one chunk [i0, i0 + cn) of T (cn <= IC), one
+    // (member, x) block at a time through X.
+    auto stage2_store = [&](const auto &t, int i0, int cn) {
+      constexpr int W = sizeof(t[0]) / sizeof(T);
 #pragma unroll
       for (int q = 0; q < MPG; ++q) {
         if (q >= nm) break;
         const FemMember &M = a.mem[m0 + q];
-        T *__restrict__ outp = (T *)M.out + e0 * M.oe;
+        const int gq = a.g_same ? 0 : q;
 #pragma unroll
         for (int x = 0; x < NX; ++x) {
 #pragma unroll
-          for (int i = 0; i < NI; ++i) {
+          for (int ic = 0; ic < W; ++ic) {
             T acc;
             if (has_g) {
-              acc = gm[q][x][0] * t[0][i];
+              acc = gm[gq][x][0] * t[0][ic];
 #pragma unroll
-              for (int r = 1; r < NR; ++r) acc = fma(gm[q][x][r], t[r][i], acc);
+              for (int r = 1; r < NR; ++r) acc = fma(gm[gq][x][r], t[r][ic], acc);
             } else {
-              acc = t[0][i];
+              acc = t[0][ic];
             }
-            lds_u[i * kPitch + lane] = acc;
+            X[ic * kPitch + lane] = acc;
           }
           __syncthreads();
-          T *__restrict__ ox = outp + x * M.ox;
-          const int oe = (int)M.oe, oi = (int)M.oi;
-          if (n == kTile) {
-#pragma unroll 4
-            for (int k = 0; k < NI; ++k) {
+          if (o_fast && cn == W) {
+            // Dense output [E][NX][NI]: the block is 64 runs of W values,
+            // one element every NX*NI (contiguous when W == NI, NX == 1).
+            T *__restrict__ ox = (T *)M.out + e0 * (NX * NI) + x * NI + i0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
               const int f = lane + kTile * k;
-              const int el = f / NI, i = f - el * NI;
-              ox[el * oe + i * oi] = lds_u[i * kPitch + el];
+              const int el = f / W, ic = f - el * W;
+              ox[el * (NX * NI) + ic] = X[ic * kPitch + el];
             }
           } else {
-            const int total = n * NI;
+            T *__restrict__ ox = (T *)M.out + e0 * M.oe + x * M.ox + (int64_t)i0 * M.oi;
+            const int oe = (int)M.oe, oi = (int)M.oi;
+            const int total = n * cn;
             for (int f = lane; f < total; f += kTile) {
-              const int el = f / NI, i = f - el * NI;
-              ox[el * oe + i * oi] = lds_u[i * kPitch + el];
+              const int el = f / cn, ic = f - el * cn;
+              ox[el * oe + ic * oi] = X[ic * kPitch + el];
             }
           }
           __syncthreads();
         }
       }
+    };
+    if constexpr (UREG) {
+      // Several equal chunks of IC outputs (NI padded to kChunks * IC, the
+      // padded rows of S are zero and the padded outputs are not stored): one
+      // loop body, so nothing is hoisted from one chunk into another.
+#pragma unroll 1
+      for (int ch = 0; ch < F::kChunks; ++ch) {
+        const int i0 = ch * IC;
+        T t[NR][IC];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int ic = 0; ic < IC; ++ic) t[r][ic] = 0;
+        // S packed [r][i-group][j][kGW]: each scalar load is the kGW values
+        // of one j row that the group's kGW accumulators consume next.
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+          for (int gi = 0; gi < IC / kGW; ++gi) {
+            const T *__restrict__ Sg =
+                S + (((int64_t)r * kNG + ch * (IC / kGW) + gi) * NJ) * kGW;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+              for (int w = 0; w < kGW; ++w)
+                t[r][gi * kGW + w] = fma(Sg[j * kGW + w], ur[UREG ? j : 0], t[r][gi * kGW + w]);
+          }
+        }
+        const int ic_n = NI - i0 < IC ? NI - i0 : IC;
+        stage2_store(t, i0, ic_n);
+      }
+    } else {
+      T t[NR][NI];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int ic = 0; ic < NI; ++ic) t[r][ic] = 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        // u is re-read from LDS for every r: a fresh address keeps the
+        // compiler from caching all NJ values in registers across r.
+        const int xl = fresh_lane();
+#pragma unroll 2
+        for (int j = 0; j < NJ; ++j) {
+          const T uj = X[j * kPitch + xl];
+          const T *__restrict__ Srow = S + ((int64_t)r * NJ + j) * NI;
+#pragma unroll
+          for (int ic = 0; ic < NI; ++ic) t[r][ic] = fma(Srow[ic], uj, t[r][ic]);
+        }
+      }
+      __syncthreads();
+      stage2_store(t, 0, NI);
     }
+    cur = nxt;
   }
 }
 
-// S of every group packed as [group][r][j][i] from the caller's strides.
+// S of every group packed from the caller's strides, either as
+// [group][r][j][i] (u read from LDS) or, with u in registers, as
+// [group][r][i / kGW][j][i % kGW] with i padded to a multiple of kGW (zeros).
 struct PackArgs {
   const void *S[BES_FEM_MAX_GROUPS];
   int64_t sr[BES_FEM_MAX_GROUPS], si[BES_FEM_MAX_GROUPS], sj[BES_FEM_MAX_GROUPS];
   int n_groups, NR, NI, NJ;
+  int nip;   // > 0: grouped layout with i padded to nip
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) pack_s_kernel(const PackArgs a, T *__restrict__ dst) {
-  const int per = a.NR * a.NJ * a.NI;
+  const bool grouped = a.nip > 0;
+  const int nip = grouped ? a.nip : a.NI;
+  const int per = a.NR * a.NJ * nip;
   const int total = per * a.n_groups;
   for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < total; f += gridDim.x * blockDim.x) {
     const int g = f / per;
     int rem = f - g * per;
-    const int r = rem / (a.NJ * a.NI);
-    rem -= r * a.NJ * a.NI;
-    const int j = rem / a.NI, i = rem - j * a.NI;
-    dst[f] = ((const T *)a.S[g])[r * a.sr[g] + i * a.si[g] + j * a.sj[g]];
+    const int r = rem / (a.NJ * nip);
+    rem -= r * a.NJ * nip;
+    int i, j;
+    if (grouped) {
+      const int gi = rem / (a.NJ * kGW);
+      rem -= gi * a.NJ * kGW;
+      j = rem / kGW;
+      i = gi * kGW + (rem - j * kGW);
+    } else {
+      j = rem / nip;
+      i = rem - j * nip;
+    }
+    dst[f] = i < a.NI ? ((const T *)a.S[g])[r * a.sr[g] + i * a.si[g] + j * a.sj[g]] : (T)0;
   }
 }
 
+// i-chunk of the stage-1 accumulator: the whole row when T[NR][NI] fits in
+// 120 VGPRs, else chunks of whole kGW-groups within 72 VGPRs (u then lives in
+// registers and S is packed grouped, padded to a whole number of chunks).
+template <typename T, int NI, int NR>
+constexpr int kIC = (NR * NI * (int)sizeof(T) / 4 <= 120)
+                        ? NI
+                        : (72 * 4 / ((int)sizeof(T) * NR)) / kGW * kGW;
+
+// Padded i extent of the packed S for these extents (0: ungrouped layout).
+int grouped_nip(bool f64, int NI, int NR) {
+#define BES_NIP_CASE(ni, nj, nr, nx)                                                  \
+  if (NI == ni && NR == nr) {                                                        \
+    const int ic = f64 ? kIC<double, ni, nr> : kIC<float, ni, nr>;                   \
+    return ic < ni ? (ni + ic - 1) / ic * ic : 0;                                    \
+  }
+  BES_FEM_SHAPES(BES_NIP_CASE)
+#undef BES_NIP_CASE
+  return 0;
+}
+
 template <typename T, int NI, int NJ, int NR, int NX>
-hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, dim3 grid,
+hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, bool pf, dim3 grid,
                         hipStream_t s) {
+  constexpr int IC = kIC<T, NI, NR>;
+  constexpr bool UREG = IC < NI;
   // Functional (element-wise) operands get their own instantiation, so the
-  // plain kernels carry no prologue code; those keep one member per group.
+  // plain kernels carry no prologue code; those keep one member per group
+  // and never prefetch (the prologue runs on the raw loads).
   if (ew)
-    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 1, true>), grid, dim3(kTile), 0, s,
-                       a, spack);
+    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 1, IC, true, false, UREG>), grid,
+                       dim3(kTile), 0, s, a, spack);
+  else if (mpg == 1 && !pf)
+    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 1, IC, false, false, UREG>), grid,
+                       dim3(kTile), 0, s, a, spack);
   else if (mpg == 1)
-    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 1, false>), grid, dim3(kTile), 0, s,
-                       a, spack);
+    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 1, IC, false, true, UREG>), grid,
+                       dim3(kTile), 0, s, a, spack);
+  else if (!pf)
+    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 3, IC, false, false, UREG>), grid,
+                       dim3(kTile), 0, s, a, spack);
   else
-    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 3, false>), grid, dim3(kTile), 0, s,
-                       a, spack);
+    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 3, IC, false, true, UREG>), grid,
+                       dim3(kTile), 0, s, a, spack);
   return hipGetLastError();
 }
 
@@ -381,6 +614,15 @@ FemArgs chunk_groups(const FemArgs &in, int mpg, int *group_of_chunk) {
   return out;
 }
 
+bool same_src(const FemSrc &x, const FemSrc &y) {
+  if (x.kind != y.kind || x.p0 != y.p0 || x.p1 != y.p1 || x.off0 != y.off0 || x.off1 != y.off1 ||
+      x.op != y.op || x.alpha != y.alpha || x.beta != y.beta)
+    return false;
+  for (int k = 0; k < 3; ++k)
+    if (x.s0[k] != y.s0[k] || x.s1[k] != y.s1[k]) return false;
+  return true;
+}
+
 }  // namespace
 
 int device_cu_count() {
@@ -397,11 +639,12 @@ int device_cu_count() {
 }
 
 size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR) {
-  return (size_t)BES_FEM_MAX_GROUPS * NR * NJ * NI * (f64 ? 8 : 4);
+  const int nip = std::max(NI, grouped_nip(f64, NI, NR));
+  return (size_t)BES_FEM_MAX_GROUPS * NR * NJ * nip * (f64 ? 8 : 4);
 }
 
 hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
-                      int blocks_per_cu, hipStream_t stream) {
+                      int blocks_per_cu, bool prefetch, hipStream_t stream) {
   if (a.E <= 0) return hipSuccess;
   if (!workspace) return hipErrorInvalidValue;
   int maxm = 0;
@@ -412,10 +655,27 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
     ew |= a.mem[m].g.kind == FEM_SRC_ELEMENTWISE;
     tet |= a.mem[m].g.kind == FEM_SRC_TET;
   }
-  const int mpg = (maxm <= 1 || ew || tet) ? 1 : 3;
+  // Every member reads the same G through one shared row: stage it once per
+  // tile (the Jacobian of all members of a functional batch, for example).
+  bool g_same = a.n_members > 0 && a.mem[0].g.kind != FEM_SRC_NONE;
+  for (int m = 1; m < a.n_members && g_same; ++m) g_same = same_src(a.mem[m].g, a.mem[0].g);
+  for (int g = 0; g < a.n_groups && g_same; ++g) g_same = a.grp[g].g_row > 0;
+  const int mpg = (maxm <= 1 || ew) ? 1 : 3;
   int chunk_src[BES_FEM_MAX_GROUPS + 1];
   FemArgs c = chunk_groups(a, mpg, chunk_src);
   if (c.n_groups > BES_FEM_MAX_GROUPS) return hipErrorInvalidValue;
+  c.g_same = g_same ? 1 : 0;
+  (void)tet;
+  for (int g = 0; g < c.n_groups; ++g) {
+    const FemSrc &u = c.grp[g].u;
+    bool d = u.s0[0] == NJ && u.s0[1] == 1;
+    if (u.kind == FEM_SRC_ELEMENTWISE && u.p1) d = d && u.s1[0] == NJ && u.s1[1] == 1;
+    c.grp[g].u_dense = d ? 1 : 0;
+  }
+  for (int m = 0; m < c.n_members; ++m) {
+    FemMember &M = c.mem[m];
+    M.o_dense = (M.oe == (int64_t)NX * NI && (NX == 1 || M.ox == NI) && M.oi == 1) ? 1 : 0;
+  }
   // Pack S of every chunk (chunks of one group repeat its S).
   PackArgs pk;
   pk.n_groups = c.n_groups;
@@ -428,7 +688,8 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
     pk.si[k] = c.grp[k].ss[1];
     pk.sj[k] = c.grp[k].ss[2];
   }
-  const int pack_total = NR * NJ * NI * c.n_groups;
+  pk.nip = grouped_nip(f64, NI, NR);
+  const int pack_total = NR * NJ * (pk.nip > 0 ? pk.nip : NI) * c.n_groups;
   dim3 pgrid((pack_total + 255) / 256);
   if (f64)
     hipLaunchKernelGGL(pack_s_kernel<double>, pgrid, dim3(256), 0, stream, pk, (double *)workspace);
@@ -437,15 +698,16 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (blocks_per_cu < 1) blocks_per_cu = 1;
+  const bool pf = prefetch;
   const int64_t tiles = (a.E + kTile - 1) / kTile;
   const int64_t cap = (int64_t)device_cu_count() * blocks_per_cu;
   dim3 grid((unsigned)std::min<int64_t>(tiles, cap));
-#define BES_FEM_DISPATCH(ni, nj, nr, nx)                                                  \
-  if (NI == ni && NJ == nj && NR == nr && NX == nx)                                       \
-    return f64 ? launch_shape<double, ni, nj, nr, nx>(c, (const double *)workspace, mpg, ew, grid, \
-                                                      stream)                             \
-               : launch_shape<float, ni, nj, nr, nx>(c, (const float *)workspace, mpg, ew, grid, \
-                                                     stream);
+#define BES_FEM_DISPATCH(ni, nj, nr, nx)                                                       \
+  if (NI == ni && NJ == nj && NR == nr && NX == nx)                                            \
+    return f64 ? launch_shape<double, ni, nj, nr, nx>(c, (const double *)workspace, mpg, ew, pf, \
+                                                      grid, stream)                            \
+               : launch_shape<float, ni, nj, nr, nx>(c, (const float *)workspace, mpg, ew, pf,  \
+                                                     grid, stream);
   BES_FEM_SHAPES(BES_FEM_DISPATCH)
 #undef BES_FEM_DISPATCH
   return hipErrorInvalidValue;

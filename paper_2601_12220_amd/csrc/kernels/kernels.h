@@ -13,10 +13,11 @@ int device_cu_count();
 
 // FEM-stream template: a pack of S into `workspace` (at least
 // fem_workspace_bytes) followed by the stream kernel with `blocks_per_cu`
-// one-wave blocks per compute unit walking 64-element tiles.
+// one-wave blocks per compute unit walking 64-element tiles; `prefetch`
+// issues the next tile's loads before the current tile's arithmetic.
 size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR);
 hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
-                      int blocks_per_cu, hipStream_t stream);
+                      int blocks_per_cu, bool prefetch, hipStream_t stream);
 
 // Generic template: one launch over (slot, tile) pairs.  `dev` is the device
 // copy of `host`.
