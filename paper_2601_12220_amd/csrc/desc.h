@@ -59,6 +59,7 @@ typedef struct FemGroup {
 
 typedef struct FemArgs {
   int64_t E;                 // number of stream elements
+  int64_t tile0, tile1;      // 64-element tiles [tile0, tile1) of this launch
   int32_t n_groups, n_members;
   int32_t g_same;            // every member reads the same G through one shared
                              // row: the row is staged once per tile

@@ -183,7 +183,9 @@ __device__ __forceinline__ int fresh_lane() {
 
 // Coalesced raw loads of W components of the 64 elements of a full tile:
 // v[k] = component c of element el for the flat position f = lane + 64 k,
-// el = f / W, c = f % W; components c >= w are not loaded.
+// el = f / W, c = f % W.  Only components c < w are meaningful; the others
+// re-read the tile's last meaningful value (clamped address) so the loads
+// stay branch-free and in bounds.
 //   dense: the tile's block is contiguous (element stride W, unit component
 //   stride): base + f, immediate offsets.
 template <typename T, int W>
@@ -193,58 +195,120 @@ __device__ __forceinline__ void load_block(T (&v)[W], const T *__restrict__ p, b
 #pragma unroll
     for (int k = 0; k < W; ++k) v[k] = p[lane + kTile * k];
   } else {
+    const int lim = (kTile - 1) * se + (w - 1) * sc;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
       const int f = lane + kTile * k;
       const int el = f / W, c = f - el * W;
-      v[k] = c < w ? p[el * se + c * sc] : (T)0;
+      const int pos = el * se + c * sc;
+      v[k] = p[pos < lim ? pos : lim];
     }
   }
 }
 
-// Raw loads of a full tile into X as [component][element] (components < w).
+// Raw loads of a full tile into X as [component][element]; rows c >= w get
+// the meaningless values (X always has at least W rows).
 template <typename T, int W>
-__device__ __forceinline__ void put_block(T *__restrict__ X, const T (&v)[W], int w, int lane) {
+__device__ __forceinline__ void put_block(T *__restrict__ X, const T (&v)[W], int lane) {
 #pragma unroll
   for (int k = 0; k < W; ++k) {
     const int f = lane + kTile * k;
     const int el = f / W, c = f - el * W;
-    if (W == 0 || c < w) X[c * kPitch + el] = v[k];
+    X[c * kPitch + el] = v[k];
   }
 }
 
-template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool PF,
+// 16-byte vector accesses of a dense tile block of W values per element:
+// lane k moves the kV consecutive values at flat positions
+// kV * (k + 64 t) + s, s < kV, for t < kVT<W> (the last t may be partly past
+// the block: those lanes re-read the block's last vector and are not used).
+template <typename T, int W>
+struct Dense {
+  static constexpr int kV = 16 / (int)sizeof(T);                 // values per vector
+  static constexpr int kN = W * kTile / kV;                       // vectors in the block
+  static constexpr int kVT = (kN + kTile - 1) / kTile;            // vectors per lane
+  static constexpr int kLen = kVT * kV;                           // values per lane
+};
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct Vec16<float> {
+  typedef float __attribute__((ext_vector_type(4))) type;
+};
+
+template <typename T, int W>
+__device__ __forceinline__ void load_dense(T *v, const T *__restrict__ p,
+                                           int lane) {
+  using D = Dense<T, W>;
+  using V = typename Vec16<T>::type;
+  const V *__restrict__ pv = (const V *)p;
+#pragma unroll
+  for (int t = 0; t < D::kVT; ++t) {
+    int q = lane + kTile * t;
+    if ((t + 1) * kTile > D::kN) q = q < D::kN ? q : D::kN - 1;
+    const V x = pv[q];
+#pragma unroll
+    for (int s = 0; s < D::kV; ++s) v[t * D::kV + s] = x[s];
+  }
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void put_dense(T *__restrict__ X, const T *v,
+                                          int lane) {
+  using D = Dense<T, W>;
+#pragma unroll
+  for (int t = 0; t < D::kVT; ++t)
+#pragma unroll
+    for (int s = 0; s < D::kV; ++s) {
+      const int f = D::kV * (lane + kTile * t) + s;
+      const int el = f / W, c = f - el * W;
+      if ((t + 1) * kTile <= D::kN || f < W * kTile) X[c * kPitch + el] = v[t * D::kV + s];
+    }
+}
+
+template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool FAST,
           bool UREG>
 struct Fem {
   static constexpr int kRows = (NJ > kMaxRow ? (NJ > IC ? NJ : IC) : (kMaxRow > IC ? kMaxRow : IC));
   static constexpr int kChunks = (NI + IC - 1) / IC;
   static_assert(kChunks == 1 || UREG, "several i-chunks need u in registers");
-  static constexpr int kPfU = PF ? NJ : 1;
-  static constexpr int kPfG = PF ? kMaxRow : 1;
 };
 
 // Waves per SIMD the register allocation of an instantiation must allow
 // (the compiler otherwise spreads a kernel over VGPRs and AGPRs and ends at
-// one wave per SIMD): accumulators T[NR][IC], G of MPG members, u in
-// registers and the prefetch buffers, in 32-bit registers, plus a margin.
-template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool PF, bool UREG>
+// one wave per SIMD): accumulators T[NR][IC], G of MPG members and u in
+// registers, in 32-bit registers, plus a margin.
+template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool UREG>
 constexpr int kWaves() {
   constexpr int w = (int)sizeof(T) / 4;
-  constexpr int live = w * (NR * IC + MPG * NX * NR + (UREG ? NJ : 0) + (PF ? NJ + kMaxRow : 0)) + 40;
+  constexpr int live = w * (NR * IC + MPG * NX * NR + (UREG ? NJ : 0)) + 40;
   constexpr int waves = 512 / live;
   return waves < 1 ? 1 : (waves > 8 ? 8 : waves);
 }
 
-template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool PF,
+// The stream kernel.  FAST instantiations contain only the straight-line
+// full-tile code: every tile they visit holds 64 elements, U rows are dense,
+// G arrives through a shared row (or is absent) and outputs are dense -- the
+// launcher checks all of it and sends the rest (the last partial tile, other
+// layouts) to the general instantiation.  Keeping the rolled paths out of the
+// FAST code matters for more than size: the compiler's memory-counter waits
+// merge over all paths of the loop, and with them present it made each tile
+// wait for the previous tile's stores before loading.
+template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool FAST,
           bool UREG>
 __global__ void __launch_bounds__(kTile)
-    __attribute__((amdgpu_waves_per_eu(kWaves<T, NI, NJ, NR, NX, MPG, IC, PF, UREG>())))
+    __attribute__((amdgpu_waves_per_eu(kWaves<T, NI, NJ, NR, NX, MPG, IC, UREG>())))
     fem_stream_kernel(const FemArgs a, const T *__restrict__ Spack) {
-  using F = Fem<T, NI, NJ, NR, NX, MPG, IC, EW, PF, UREG>;
+  using F = Fem<T, NI, NJ, NR, NX, MPG, IC, EW, FAST, UREG>;
   constexpr int kNG = F::kChunks * IC / kGW;   // i-groups (UREG layout)
   static_assert(!UREG || IC % kGW == 0, "chunks must hold whole i-groups");
   __shared__ T X[F::kRows * kPitch];
-  const int64_t n_tiles = (a.E + kTile - 1) / kTile;
+  const int64_t tile_end = a.tile1;
   const int n_groups = a.n_groups;
 
   // Shared-row width of a unit: g_same plans stage one row per tile (at the
@@ -253,64 +317,54 @@ __global__ void __launch_bounds__(kTile)
     if (a.g_same) return g == 0 ? a.grp[0].g_row : 0;
     return a.grp[g].g_row;
   };
-  // Raw G-row and U loads of a unit (full tile, no element-wise U).
-  auto load_unit = [&](const Unit &w, int lane, T (&vu)[NJ], T (&vg)[kMaxRow]) {
-    const FemGroup &H = a.grp[w.g];
-    const int64_t f0 = w.tile * kTile;
-    const int hrow = a.mem[H.m0].g.kind != FEM_SRC_NONE ? row_of(w.g) : 0;
-    if (hrow > 0) {
-      const FemSrc &s0 = a.mem[H.m0].g;
-      const T *__restrict__ pb = (const T *)s0.p0 + H.g_off + f0 * s0.s0[0];
-      load_block<T, kMaxRow>(vg, pb, false, (int)s0.s0[0], 1, hrow, lane);
-    }
-    const T *__restrict__ pu0 = (const T *)H.u.p0 + H.u.off0 + f0 * H.u.s0[0];
-    load_block<T, NJ>(vu, pu0, H.u_dense != 0, (int)H.u.s0[0], (int)H.u.s0[1], NJ, lane);
-  };
-
-  // Prefetch registers (raw loads of the next unit, full tiles only).
-  T pu[F::kPfU];
-  T pg[F::kPfG];
-  bool have_pf = false;
 
   T gm[MPG][NX][NR];   // G of the group's members (or of the plan, g_same)
 
-  Unit cur{(int64_t)blockIdx.x, 0};
-  while (cur.tile < n_tiles) {
+  Unit cur{a.tile0 + (int64_t)blockIdx.x, 0};
+  while (cur.tile < tile_end) {
     const int lane = fresh_lane();
     const int64_t e0 = cur.tile * kTile;
-    const int n = (int)(a.E - e0 < kTile ? a.E - e0 : kTile);
-    const bool full = n == kTile;
+    const int n = FAST ? kTile : (int)(a.E - e0 < kTile ? a.E - e0 : kTile);
+    const bool full = FAST || n == kTile;
     const FemGroup &G = a.grp[cur.g];
     const int m0 = G.m0, nm = G.m1 - G.m0;
     const bool has_g = a.mem[m0].g.kind != FEM_SRC_NONE;
     const int grow = has_g ? row_of(cur.g) : 0;
-    const bool g_each = has_g && G.g_row == 0 && !(a.g_same && cur.g > 0);
+    const bool g_each = !FAST && has_g && G.g_row == 0 && !(a.g_same && cur.g > 0);
     const bool u_ew = EW && G.u.kind == FEM_SRC_ELEMENTWISE;
-    const bool fast_u = full && !u_ew;
 
-    // ---- raw loads of this unit (unless prefetched) ------------------------
-    T ru[NJ];
+    // ---- raw loads: G row and U rows, all issued before any is used --------
+    constexpr int kRU = FAST ? Dense<T, NJ>::kLen : NJ;
+    T ru[kRU];
     T rg[kMaxRow];
-    if (have_pf) {
+    T rw[EW ? kRU : 1];
+    if (full && grow > 0) {
+      const FemSrc &s0 = a.mem[m0].g;
+      const T *__restrict__ pb = (const T *)s0.p0 + G.g_off + e0 * s0.s0[0];
+      load_block<T, kMaxRow>(rg, pb, false, (int)s0.s0[0], 1, grow, lane);
+    }
+    const bool u_fast = full && (FAST || G.u_dense);
+    if (u_fast) {
+      const T *__restrict__ p0 = (const T *)G.u.p0 + G.u.off0 + e0 * NJ;
+      if constexpr (FAST) load_dense<T, NJ>(ru, p0, lane);
+      else load_block<T, NJ>(ru, p0, true, NJ, 1, NJ, lane);
+      if constexpr (EW) {
+        if (u_ew && G.u.p1) {
+          const T *__restrict__ p1 = (const T *)G.u.p1 + G.u.off1 + e0 * NJ;
+          if constexpr (FAST) load_dense<T, NJ>(rw, p1, lane);
+          else load_block<T, NJ>(rw, p1, true, NJ, 1, NJ, lane);
+        } else {
 #pragma unroll
-      for (int k = 0; k < NJ; ++k) ru[k] = pu[PF ? k : 0];
-#pragma unroll
-      for (int k = 0; k < kMaxRow; ++k) rg[k] = pg[PF ? k : 0];
-    } else if (full) {
-      if (fast_u) {
-        load_unit(cur, lane, ru, rg);
-      } else if (grow > 0) {
-        const FemSrc &s0 = a.mem[m0].g;
-        const T *__restrict__ pb = (const T *)s0.p0 + G.g_off + e0 * s0.s0[0];
-        load_block<T, kMaxRow>(rg, pb, false, (int)s0.s0[0], 1, grow, lane);
+          for (int k = 0; k < kRU; ++k) rw[k] = (T)0;
+        }
       }
     }
 
     // ---- G to registers ---------------------------------------------------
     if (grow > 0) {
       if (full) {
-        put_block<T, kMaxRow>(X, rg, grow, lane);
-      } else {
+        put_block<T, kMaxRow>(X, rg, lane);
+      } else if constexpr (!FAST) {
         const FemSrc &s0 = a.mem[m0].g;
         const T *__restrict__ pb = (const T *)s0.p0 + G.g_off + e0 * s0.s0[0];
         const int se = (int)s0.s0[0];
@@ -328,71 +382,57 @@ __global__ void __launch_bounds__(kTile)
           if (q < nm) g_from_row<T, NX, NR>(X, a.mem[m0 + q].g, lane, gm[q]);
       }
       __syncthreads();
-    } else if (g_each) {
-      for (int q = 0; q < nm && q < MPG; ++q) {
-        const FemSrc &s = a.mem[m0 + q].g;
-        const bool tet = s.kind == FEM_SRC_TET;
-        if (tet) {
-          stage_rows_rolled<T, 12, 3, false>(X, s, e0, n, lane);
-        } else {
-          stage_rows_rolled<T, NX * NR, NR, EW>(X, s, e0, n, lane);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int qq = 0; qq < MPG; ++qq) {
-          if (qq != q) continue;
-          if (kTetCapable<NX, NR> && tet) {
-            if constexpr (kTetCapable<NX, NR>) tet_from_lds<T, NX, NR>(X, lane, s.s1[0] != 0, gm[qq]);
+    } else if constexpr (!FAST) {
+      if (g_each) {
+        for (int q = 0; q < nm && q < MPG; ++q) {
+          const FemSrc &s = a.mem[m0 + q].g;
+          const bool tet = s.kind == FEM_SRC_TET;
+          if (tet) {
+            stage_rows_rolled<T, 12, 3, false>(X, s, e0, n, lane);
           } else {
-#pragma unroll
-            for (int x = 0; x < NX; ++x)
-#pragma unroll
-              for (int r = 0; r < NR; ++r) gm[qq][x][r] = X[(x * NR + r) * kPitch + lane];
+            stage_rows_rolled<T, NX * NR, NR, EW>(X, s, e0, n, lane);
           }
+          __syncthreads();
+#pragma unroll
+          for (int qq = 0; qq < MPG; ++qq) {
+            if (qq != q) continue;
+            if (kTetCapable<NX, NR> && tet) {
+              if constexpr (kTetCapable<NX, NR>)
+                tet_from_lds<T, NX, NR>(X, lane, s.s1[0] != 0, gm[qq]);
+            } else {
+#pragma unroll
+              for (int x = 0; x < NX; ++x)
+#pragma unroll
+                for (int r = 0; r < NR; ++r) gm[qq][x][r] = X[(x * NR + r) * kPitch + lane];
+            }
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
     }
 
     // ---- U rows into X (prologue applied) ---------------------------------
-    if (fast_u) {
-      put_block<T, NJ>(X, ru, NJ, lane);
-    } else if (EW && u_ew && full && G.u_dense) {
-      // Element-wise U from dense sources: both raw loads coalesced, then
-      // alpha * op(S0) + beta (+ S1) per value in the coalesced mapping.
-      const T *__restrict__ p0 = (const T *)G.u.p0 + G.u.off0 + e0 * NJ;
-      load_block<T, NJ>(ru, p0, true, NJ, 1, NJ, lane);
-      T w[NJ];
-      if (G.u.p1) {
-        const T *__restrict__ p1 = (const T *)G.u.p1 + G.u.off1 + e0 * NJ;
-        load_block<T, NJ>(w, p1, true, NJ, 1, NJ, lane);
-      } else {
+    if (u_fast) {
+      if constexpr (EW) {
+        if (u_ew) {
+          const T alpha = (T)G.u.alpha, beta = (T)G.u.beta;
+          const int op = G.u.op;
 #pragma unroll
-        for (int k = 0; k < NJ; ++k) w[k] = (T)0;
+          for (int k = 0; k < kRU; ++k) ru[k] = alpha * apply_op<T>(op, ru[k]) + beta + rw[k];
+        }
       }
-      const T alpha = (T)G.u.alpha, beta = (T)G.u.beta;
-      const int op = G.u.op;
-#pragma unroll
-      for (int k = 0; k < NJ; ++k) ru[k] = alpha * apply_op<T>(op, ru[k]) + beta + w[k];
-      put_block<T, NJ>(X, ru, NJ, lane);
-    } else {
+      if constexpr (FAST) put_dense<T, NJ>(X, ru, lane);
+      else put_block<T, NJ>(X, ru, lane);
+    } else if constexpr (!FAST) {
       stage_rows_rolled<T, NJ, 1, EW>(X, G.u, e0, n, lane);  // U strides (e, j)
     }
     __syncthreads();
 
-    // ---- next unit and its prefetch -----------------------------------------
+    // ---- next unit --------------------------------------------------------
     Unit nxt = cur;
     if (++nxt.g >= n_groups) {
       nxt.g = 0;
       nxt.tile += gridDim.x;
-    }
-    have_pf = false;
-    if constexpr (PF) {
-      if (nxt.tile < n_tiles && (nxt.tile + 1) * kTile <= a.E &&
-          !(EW && a.grp[nxt.g].u.kind == FEM_SRC_ELEMENTWISE)) {
-        load_unit(nxt, lane, pu, pg);
-        have_pf = true;
-      }
     }
 
     // ---- u into registers (several chunks) ----------------------------------
@@ -406,9 +446,11 @@ __global__ void __launch_bounds__(kTile)
     const T *__restrict__ S = Spack + (int64_t)cur.g * NR * NJ * (UREG ? kNG * kGW : NI);
     (void)kNG;
     bool o_fast = full;
+    if constexpr (!FAST) {
 #pragma unroll
-    for (int q = 0; q < MPG; ++q)
-      if (q < nm) o_fast = o_fast && a.mem[m0 + q].o_dense;
+      for (int q = 0; q < MPG; ++q)
+        if (q < nm) o_fast = o_fast && a.mem[m0 + q].o_dense;
+    }
     // Stage 2 and stores of one chunk [i0, i0 + cn) of T (cn <= IC), one
     // (member, x) block at a time through X.
     auto stage2_store = [&](const auto &t, int i0, int cn) {
@@ -433,17 +475,34 @@ __global__ void __launch_bounds__(kTile)
             X[ic * kPitch + lane] = acc;
           }
           __syncthreads();
-          if (o_fast && cn == W) {
-            // Dense output [E][NX][NI]: the block is 64 runs of W values,
-            // one element every NX*NI (contiguous when W == NI, NX == 1).
+          if (FAST && NX == 1 && W == NI) {
+            // Contiguous output block of 64 * NI values: 16-byte stores.
+            using V = typename Vec16<T>::type;
+            using D = Dense<T, NI>;
+            V *__restrict__ ov = (V *)((T *)M.out + e0 * NI);
+#pragma unroll
+            for (int t = 0; t < D::kVT; ++t) {
+              const int q = lane + kTile * t;
+              V vv;
+#pragma unroll
+              for (int sv = 0; sv < D::kV; ++sv) {
+                const int f = D::kV * q + sv;
+                const int el = f / NI, ic = f - el * NI;
+                vv[sv] = X[ic * kPitch + (el < kTile ? el : 0)];
+              }
+              if ((t + 1) * kTile <= D::kN || q < D::kN) ov[q] = vv;
+            }
+          } else if (FAST || o_fast) {
+            // Dense output [E][NX][NI]: the block is 64 runs of cn values,
+            // one element every NX*NI (contiguous when cn == NI, NX == 1).
             T *__restrict__ ox = (T *)M.out + e0 * (NX * NI) + x * NI + i0;
 #pragma unroll
             for (int k = 0; k < W; ++k) {
               const int f = lane + kTile * k;
               const int el = f / W, ic = f - el * W;
-              ox[el * (NX * NI) + ic] = X[ic * kPitch + el];
+              if (W == NI || ic < cn) ox[el * (NX * NI) + ic] = X[ic * kPitch + el];
             }
-          } else {
+          } else if constexpr (!FAST) {
             T *__restrict__ ox = (T *)M.out + e0 * M.oe + x * M.ox + (int64_t)i0 * M.oi;
             const int oe = (int)M.oe, oi = (int)M.oi;
             const int total = n * cn;
@@ -568,28 +627,26 @@ int grouped_nip(bool f64, int NI, int NR) {
 }
 
 template <typename T, int NI, int NJ, int NR, int NX>
-hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, bool pf, dim3 grid,
+hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, bool fast, dim3 grid,
                         hipStream_t s) {
   constexpr int IC = kIC<T, NI, NR>;
   constexpr bool UREG = IC < NI;
-  // Functional (element-wise) operands get their own instantiation, so the
-  // plain kernels carry no prologue code; those keep one member per group
-  // and never prefetch (the prologue runs on the raw loads).
-  if (ew)
-    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 1, IC, true, false, UREG>), grid,
-                       dim3(kTile), 0, s, a, spack);
-  else if (mpg == 1 && !pf)
-    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 1, IC, false, false, UREG>), grid,
-                       dim3(kTile), 0, s, a, spack);
-  else if (mpg == 1)
-    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 1, IC, false, true, UREG>), grid,
-                       dim3(kTile), 0, s, a, spack);
-  else if (!pf)
-    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 3, IC, false, false, UREG>), grid,
-                       dim3(kTile), 0, s, a, spack);
-  else
-    hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, 3, IC, false, true, UREG>), grid,
-                       dim3(kTile), 0, s, a, spack);
+  // Functional (element-wise) operands get their own instantiations, so the
+  // plain kernels carry no prologue code; those keep one member per group.
+#define BES_FEM_LAUNCH(MPG, EW, FAST)                                                         \
+  hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, MPG, IC, EW, FAST, UREG>), grid,     \
+                     dim3(kTile), 0, s, a, spack)
+  if (ew) {
+    if (fast) BES_FEM_LAUNCH(1, true, true);
+    else BES_FEM_LAUNCH(1, true, false);
+  } else if (mpg == 1) {
+    if (fast) BES_FEM_LAUNCH(1, false, true);
+    else BES_FEM_LAUNCH(1, false, false);
+  } else {
+    if (fast) BES_FEM_LAUNCH(3, false, true);
+    else BES_FEM_LAUNCH(3, false, false);
+  }
+#undef BES_FEM_LAUNCH
   return hipGetLastError();
 }
 
@@ -698,19 +755,52 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (blocks_per_cu < 1) blocks_per_cu = 1;
-  const bool pf = prefetch;
+  (void)prefetch;
+  // Full dense tiles go to the straight-line FAST instantiation; the last
+  // partial tile and any other layout to the general one.
+  bool fast_ok = true;
+  for (int g = 0; g < c.n_groups && fast_ok; ++g) {
+    const FemGroup &G = c.grp[g];
+    fast_ok = G.u_dense != 0;
+    const bool has_g = c.mem[G.m0].g.kind != FEM_SRC_NONE;
+    const int row = c.g_same ? (g == 0 ? c.grp[0].g_row : 1) : G.g_row;
+    if (has_g && row <= 0) fast_ok = false;
+  }
+  for (int m = 0; m < c.n_members && fast_ok; ++m) fast_ok = c.mem[m].o_dense != 0;
+  // The FAST code moves dense U rows and contiguous outputs 16 bytes at a time.
+  const size_t esz = f64 ? 8 : 4;
+  auto al16 = [](const void *p, int64_t off, size_t esz) {
+    return (((uintptr_t)p + (uintptr_t)(off * (int64_t)esz)) & 15u) == 0;
+  };
+  for (int g = 0; g < c.n_groups && fast_ok; ++g) {
+    const FemSrc &u = c.grp[g].u;
+    fast_ok = al16(u.p0, u.off0, esz) && (!u.p1 || u.kind != FEM_SRC_ELEMENTWISE || al16(u.p1, u.off1, esz));
+  }
+  for (int m = 0; m < c.n_members && fast_ok; ++m) fast_ok = al16(c.mem[m].out, 0, esz);
   const int64_t tiles = (a.E + kTile - 1) / kTile;
+  const int64_t full_tiles = fast_ok ? a.E / kTile : 0;
   const int64_t cap = (int64_t)device_cu_count() * blocks_per_cu;
-  dim3 grid((unsigned)std::min<int64_t>(tiles, cap));
-#define BES_FEM_DISPATCH(ni, nj, nr, nx)                                                       \
-  if (NI == ni && NJ == nj && NR == nr && NX == nx)                                            \
-    return f64 ? launch_shape<double, ni, nj, nr, nx>(c, (const double *)workspace, mpg, ew, pf, \
-                                                      grid, stream)                            \
-               : launch_shape<float, ni, nj, nr, nx>(c, (const float *)workspace, mpg, ew, pf,  \
-                                                     grid, stream);
-  BES_FEM_SHAPES(BES_FEM_DISPATCH)
+  auto launch = [&](bool fast, int64_t t0, int64_t t1) -> hipError_t {
+    FemArgs d = c;
+    d.tile0 = t0;
+    d.tile1 = t1;
+    dim3 grid((unsigned)std::min<int64_t>(t1 - t0, cap));
+#define BES_FEM_DISPATCH(ni, nj, nr, nx)                                                      \
+    if (NI == ni && NJ == nj && NR == nr && NX == nx)                                         \
+      return f64 ? launch_shape<double, ni, nj, nr, nx>(d, (const double *)workspace, mpg, ew, \
+                                                        fast, grid, stream)                   \
+                 : launch_shape<float, ni, nj, nr, nx>(d, (const float *)workspace, mpg, ew,   \
+                                                       fast, grid, stream);
+    BES_FEM_SHAPES(BES_FEM_DISPATCH)
 #undef BES_FEM_DISPATCH
-  return hipErrorInvalidValue;
+    return hipErrorInvalidValue;
+  };
+  if (full_tiles > 0) {
+    e = launch(true, 0, full_tiles);
+    if (e != hipSuccess) return e;
+  }
+  if (full_tiles < tiles) return launch(false, full_tiles, tiles);
+  return hipSuccess;
 }
 
 }  // namespace bes
