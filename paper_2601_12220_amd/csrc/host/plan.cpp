@@ -314,7 +314,7 @@ bes_config default_config(const Plan &p) {
   } else if (p.fem_ok) {
     c.template_id = BES_T_FEM_STREAM;
     c.p[0] = 64;   // elements per tile (one wave)
-    c.p[1] = 8;    // resident one-wave blocks per CU
+    c.p[1] = 32;   // one-wave blocks per CU in the grid (measured best)
   } else if (template_supported(p, BES_T_GENERIC)) {
     c.template_id = BES_T_GENERIC;
     c.p[0] = 256;

@@ -176,7 +176,7 @@ struct Unit {
 // hoisted out of the tile loop and held in VGPRs for the whole kernel (which
 // would cap occupancy at one wave per SIMD).
 __device__ __forceinline__ int fresh_lane() {
-  int l = (int)threadIdx.x;
+  int l = (int)threadIdx.x & (kTile - 1);
   asm volatile("" : "+v"(l));
   return l;
 }
@@ -251,7 +251,7 @@ __device__ __forceinline__ void load_dense(T *v, const T *__restrict__ p,
   for (int t = 0; t < D::kVT; ++t) {
     int q = lane + kTile * t;
     if ((t + 1) * kTile > D::kN) q = q < D::kN ? q : D::kN - 1;
-    const V x = pv[q];
+    const V x = __builtin_nontemporal_load(&pv[q]);   // streamed once
 #pragma unroll
     for (int s = 0; s < D::kV; ++s) v[t * D::kV + s] = x[s];
   }
@@ -286,7 +286,7 @@ struct Fem {
 template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool UREG>
 constexpr int kWaves() {
   constexpr int w = (int)sizeof(T) / 4;
-  constexpr int live = w * (NR * IC + MPG * NX * NR + (UREG ? NJ : 0)) + 40;
+  constexpr int live = w * (NR * IC + MPG * NX * NR + (UREG ? NJ : 0)) + 48;
   constexpr int waves = 512 / live;
   return waves < 1 ? 1 : (waves > 8 ? 8 : waves);
 }
@@ -299,15 +299,23 @@ constexpr int kWaves() {
 // FAST code matters for more than size: the compiler's memory-counter waits
 // merge over all paths of the loop, and with them present it made each tile
 // wait for the previous tile's stores before loading.
+//
+// WPB > 1 (shapes whose S outgrows the scalar data cache): a block of WPB
+// waves, one 64-element tile each, with its own staging region.  The waves of
+// a block pass the same barriers, so they walk S together and share each
+// chunk of it in the scalar cache instead of each thrashing its own.
 template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool FAST,
-          bool UREG>
-__global__ void __launch_bounds__(kTile)
+          bool UREG, int WPB>
+__global__ void __launch_bounds__(kTile * WPB)
     __attribute__((amdgpu_waves_per_eu(kWaves<T, NI, NJ, NR, NX, MPG, IC, UREG>())))
     fem_stream_kernel(const FemArgs a, const T *__restrict__ Spack) {
   using F = Fem<T, NI, NJ, NR, NX, MPG, IC, EW, FAST, UREG>;
   constexpr int kNG = F::kChunks * IC / kGW;   // i-groups (UREG layout)
   static_assert(!UREG || IC % kGW == 0, "chunks must hold whole i-groups");
-  __shared__ T X[F::kRows * kPitch];
+  static_assert(FAST || WPB == 1, "partial tiles run one wave per block");
+  __shared__ T Xall[WPB * F::kRows * kPitch];
+  const int wave = WPB > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / kTile) : 0;
+  T *const X = Xall + wave * F::kRows * kPitch;
   const int64_t tile_end = a.tile1;
   const int n_groups = a.n_groups;
 
@@ -320,10 +328,14 @@ __global__ void __launch_bounds__(kTile)
 
   T gm[MPG][NX][NR];   // G of the group's members (or of the plan, g_same)
 
-  Unit cur{a.tile0 + (int64_t)blockIdx.x, 0};
+  Unit cur{a.tile0 + (int64_t)blockIdx.x * WPB, 0};
   while (cur.tile < tile_end) {
-    const int lane = fresh_lane();
-    const int64_t e0 = cur.tile * kTile;
+    int lane = fresh_lane();
+    // This wave's tile; a wave past the end repeats the last tile's work
+    // (valid addresses, same barriers) and stores nothing.
+    const int64_t mine = cur.tile + wave;
+    const bool live = WPB == 1 || mine < tile_end;
+    const int64_t e0 = (live ? mine : tile_end - 1) * kTile;
     const int n = FAST ? kTile : (int)(a.E - e0 < kTile ? a.E - e0 : kTile);
     const bool full = FAST || n == kTile;
     const FemGroup &G = a.grp[cur.g];
@@ -432,7 +444,7 @@ __global__ void __launch_bounds__(kTile)
     Unit nxt = cur;
     if (++nxt.g >= n_groups) {
       nxt.g = 0;
-      nxt.tile += gridDim.x;
+      nxt.tile += (int64_t)gridDim.x * WPB;
     }
 
     // ---- u into registers (several chunks) ----------------------------------
@@ -490,7 +502,9 @@ __global__ void __launch_bounds__(kTile)
                 const int el = f / NI, ic = f - el * NI;
                 vv[sv] = X[ic * kPitch + (el < kTile ? el : 0)];
               }
-              if ((t + 1) * kTile <= D::kN || q < D::kN) ov[q] = vv;
+              // written once, never re-read here: streaming store
+              if (live && ((t + 1) * kTile <= D::kN || q < D::kN))
+                __builtin_nontemporal_store(vv, &ov[q]);
             }
           } else if (FAST || o_fast) {
             // Dense output [E][NX][NI]: the block is 64 runs of cn values,
@@ -500,7 +514,8 @@ __global__ void __launch_bounds__(kTile)
             for (int k = 0; k < W; ++k) {
               const int f = lane + kTile * k;
               const int el = f / W, ic = f - el * W;
-              if (W == NI || ic < cn) ox[el * (NX * NI) + ic] = X[ic * kPitch + el];
+              const T val = X[ic * kPitch + el];
+              if (live && (W == NI || ic < cn)) ox[el * (NX * NI) + ic] = val;
             }
           } else if constexpr (!FAST) {
             T *__restrict__ ox = (T *)M.out + e0 * M.oe + x * M.ox + (int64_t)i0 * M.oi;
@@ -522,6 +537,7 @@ __global__ void __launch_bounds__(kTile)
 #pragma unroll 1
       for (int ch = 0; ch < F::kChunks; ++ch) {
         const int i0 = ch * IC;
+        lane = fresh_lane();   // per-chunk addresses: nothing hoisted across chunks
         T t[NR][IC];
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -607,12 +623,12 @@ __global__ void __launch_bounds__(256) pack_s_kernel(const PackArgs a, T *__rest
 }
 
 // i-chunk of the stage-1 accumulator: the whole row when T[NR][NI] fits in
-// 120 VGPRs, else chunks of whole kGW-groups within 72 VGPRs (u then lives in
+// 120 VGPRs, else chunks of whole kGW-groups within 48 VGPRs (u then lives in
 // registers and S is packed grouped, padded to a whole number of chunks).
 template <typename T, int NI, int NR>
 constexpr int kIC = (NR * NI * (int)sizeof(T) / 4 <= 120)
                         ? NI
-                        : (72 * 4 / ((int)sizeof(T) * NR)) / kGW * kGW;
+                        : (48 * 4 / ((int)sizeof(T) * NR)) / kGW * kGW;
 
 // Padded i extent of the packed S for these extents (0: ungrouped layout).
 int grouped_nip(bool f64, int NI, int NR) {
@@ -626,16 +642,27 @@ int grouped_nip(bool f64, int NI, int NR) {
   return 0;
 }
 
+// Waves per block: one, unless S (read through the scalar data cache by every
+// FMA of stage 1) is larger than about 12 KB; then eight waves (one block per
+// compute unit at two waves per SIMD) share it.
+template <typename T, int NI, int NJ, int NR>
+constexpr int kWPB = (NR * NI * NJ * (int)sizeof(T) > 12 * 1024) ? 8 : 1;
+
 template <typename T, int NI, int NJ, int NR, int NX>
 hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, bool fast, dim3 grid,
                         hipStream_t s) {
   constexpr int IC = kIC<T, NI, NR>;
   constexpr bool UREG = IC < NI;
+  constexpr int WPB = kWPB<T, NI, NJ, NR>;
+  // FAST launches of multi-wave blocks cover WPB tiles per block.
+  dim3 g = grid;
+  if (fast && WPB > 1) g.x = (unsigned)std::max<int64_t>(1, ((int64_t)grid.x + WPB - 1) / WPB);
   // Functional (element-wise) operands get their own instantiations, so the
   // plain kernels carry no prologue code; those keep one member per group.
-#define BES_FEM_LAUNCH(MPG, EW, FAST)                                                         \
-  hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, MPG, IC, EW, FAST, UREG>), grid,     \
-                     dim3(kTile), 0, s, a, spack)
+#define BES_FEM_LAUNCH(MPG, EW, FAST)                                                            \
+  hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, MPG, IC, EW, FAST, UREG,              \
+                                        FAST ? WPB : 1>),                                        \
+                     FAST ? g : grid, dim3(kTile * (FAST ? WPB : 1)), 0, s, a, spack)
   if (ew) {
     if (fast) BES_FEM_LAUNCH(1, true, true);
     else BES_FEM_LAUNCH(1, true, false);

@@ -1,0 +1,118 @@
+"""Autotuner for batched-einsum plans.
+
+The paper retrieves transformation choices for a batched einsum from a
+database of performance facts keyed by its canonical form (Section
+"Integration with a Code Transformation Framework"; the retrieval listing
+there).  This module produces those facts on the GPU: it times every
+candidate configuration of a plan's kernel template through the C ABI with
+HIP events on the launching stream and appends the fastest one to the
+context's tuning database under the plan's canonical key.  Because the key is
+the canonical form, every renamed, permuted or re-shared registration of the
+same batched einsum retrieves the same record (``Plan.lookup``).
+
+Only the timing loop runs here; every evaluation is the library's own kernel.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+from . import capi
+
+T_FEM_STREAM = 1
+T_GENERIC = 2
+T_MFMA = 3
+
+
+def candidates(template_id: int) -> List[Tuple[int, ...]]:
+    """Parameter tuples (template id first) the tuner tries for a template.
+
+    FEM stream: p[1] = one-wave blocks per compute unit in the grid.
+    Generic:    p[0] = outputs per tile, p[1] = lanes per output.
+    MFMA:       the single 128 x 128 tile shape the template implements."""
+    if template_id == T_FEM_STREAM:
+        return [(T_FEM_STREAM, 64, b, 0) for b in (8, 16, 32, 64)]
+    if template_id == T_GENERIC:
+        return [(T_GENERIC, tile, lanes) for tile in (64, 256, 1024) for lanes in (1, 4, 16, 64)]
+    if template_id == T_MFMA:
+        return [(T_MFMA, 128, 128)]
+    return []
+
+
+@dataclass
+class TuneResult:
+    key: str
+    best: Tuple[int, ...]
+    seconds: float
+    timings: Dict[Tuple[int, ...], float] = field(default_factory=dict)
+
+
+def time_launches(launch, stream, reps: int, warmup: int) -> float:
+    """Mean seconds per call of ``launch()`` between HIP events recorded on
+    ``stream`` (a torch stream), after ``warmup`` untimed calls."""
+    import torch
+    for _ in range(warmup):
+        launch()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        launch()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) * 1e-3 / reps
+
+
+def tune(ctx, plan, buffers: Dict[str, object], outputs: Sequence[object], stream=None,
+         reps: int = 10, warmup: int = 2, arch: str = "gfx950",
+         record: bool = True) -> Optional[TuneResult]:
+    """Time every candidate of the plan's current template on ``buffers`` /
+    ``outputs`` (device tensors), install the fastest in the plan and, with
+    ``record``, append it to the context's database.  Returns None when the
+    template has nothing to tune."""
+    import torch
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    handle = int(stream.cuda_stream)
+    cands = candidates(plan.config.template_id)
+    if not cands:
+        return None
+    src = plan.src_ptrs(buffers)
+    outs = [o.data_ptr() for o in outputs]
+    timings: Dict[Tuple[int, ...], float] = {}
+    for c in cands:
+        try:
+            plan.set_config(*c)
+        except capi.BesError:
+            continue                      # the template rejects this shape
+        timings[c] = time_launches(lambda: plan.launch_ptrs(src, outs, handle), stream, reps,
+                                   warmup)
+    if not timings:
+        return None
+    best = min(timings, key=timings.get)
+    plan.set_config(*best)
+    if record:
+        cfg = capi.bes_config()
+        cfg.template_id = best[0]
+        for k, v in enumerate(best[1:]):
+            cfg.p[k] = int(v)
+        ctx.record(plan.key, cfg, timings[best], arch)
+    return TuneResult(plan.key, best, timings[best], timings)
+
+
+def tune_all(ctx, work: Sequence[Tuple[object, Dict[str, object], Sequence[object]]],
+             stream=None, reps: int = 10, warmup: int = 2,
+             arch: str = "gfx950") -> Tuple[List[TuneResult], int]:
+    """Tune a list of (plan, buffers, outputs).  A plan whose canonical key
+    already has a record (an isomorphic plan tuned earlier in the list, or a
+    previous session's database) is not re-tuned: it retrieves the record.
+    Returns the new results and the number of retrievals."""
+    results: List[TuneResult] = []
+    hits = 0
+    for plan, bufs, outs in work:
+        if plan.lookup(arch) == capi.BES_OK:
+            hits += 1
+            continue
+        r = tune(ctx, plan, bufs, outs, stream=stream, reps=reps, warmup=warmup, arch=arch)
+        if r is not None:
+            results.append(r)
+    return results, hits
