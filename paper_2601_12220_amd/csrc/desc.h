@@ -43,8 +43,8 @@ typedef struct FemMember {
 
 typedef struct FemGroup {
   const void *S;    // the caller's S (offset applied)
-  int64_t ss[3];    // S strides along (r, i, j); the launcher packs S once per
-                    // launch into [r][j][i] for the kernel
+  int64_t ss[3];    // S strides along (r, i, j); S that is not dense in that
+                    // order is packed into it by the launcher
   FemSrc u;
   int32_t m0, m1;   // members [m0, m1) use this group
   int32_t g_row;    // > 0: the G operands of all members of the group read
@@ -55,6 +55,8 @@ typedef struct FemGroup {
   int32_t u_dense;  // set by the launcher: U's source rows are dense
                     // (s0 = (NJ, 1), and s1 likewise for a second source)
   int64_t g_off;
+  int32_t s_dense;  // set by the launcher: S is dense [r][i][j] (read in place)
+  int32_t pad2;
 } FemGroup;
 
 typedef struct FemArgs {

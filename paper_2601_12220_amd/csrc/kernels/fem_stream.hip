@@ -46,7 +46,6 @@ namespace {
 constexpr int kTile = 64;      // elements per wave tile = lanes per wave
 constexpr int kPitch = kTile + 1;
 constexpr int kMaxRow = 12;    // staged G row width (TET: 4 x 3 vertex coords)
-constexpr int kGW = 4;         // i-group width of the S layout used with u in registers
 
 template <typename T>
 __device__ __forceinline__ T apply_op(int op, T v) {
@@ -271,22 +270,20 @@ __device__ __forceinline__ void put_dense(T *__restrict__ X, const T *v,
     }
 }
 
-template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool FAST,
-          bool UREG>
+template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool FAST>
 struct Fem {
   static constexpr int kRows = (NJ > kMaxRow ? (NJ > IC ? NJ : IC) : (kMaxRow > IC ? kMaxRow : IC));
   static constexpr int kChunks = (NI + IC - 1) / IC;
-  static_assert(kChunks == 1 || UREG, "several i-chunks need u in registers");
 };
 
 // Waves per SIMD the register allocation of an instantiation must allow
 // (the compiler otherwise spreads a kernel over VGPRs and AGPRs and ends at
-// one wave per SIMD): accumulators T[NR][IC], G of MPG members and u in
-// registers, in 32-bit registers, plus a margin.
-template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool UREG>
+// one wave per SIMD): accumulators T[NR][IC], G of MPG members and u, in
+// 32-bit registers, plus a margin.
+template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC>
 constexpr int kWaves() {
   constexpr int w = (int)sizeof(T) / 4;
-  constexpr int live = w * (NR * IC + MPG * NX * NR + (UREG ? NJ : 0)) + 48;
+  constexpr int live = w * (NR * IC + MPG * NX * NR + (IC < NI ? NJ : 0)) + 48;
   constexpr int waves = 512 / live;
   return waves < 1 ? 1 : (waves > 8 ? 8 : waves);
 }
@@ -305,13 +302,11 @@ constexpr int kWaves() {
 // a block pass the same barriers, so they walk S together and share each
 // chunk of it in the scalar cache instead of each thrashing its own.
 template <typename T, int NI, int NJ, int NR, int NX, int MPG, int IC, bool EW, bool FAST,
-          bool UREG, int WPB>
+          int WPB>
 __global__ void __launch_bounds__(kTile * WPB)
-    __attribute__((amdgpu_waves_per_eu(kWaves<T, NI, NJ, NR, NX, MPG, IC, UREG>())))
+    __attribute__((amdgpu_waves_per_eu(kWaves<T, NI, NJ, NR, NX, MPG, IC>())))
     fem_stream_kernel(const FemArgs a, const T *__restrict__ Spack) {
-  using F = Fem<T, NI, NJ, NR, NX, MPG, IC, EW, FAST, UREG>;
-  constexpr int kNG = F::kChunks * IC / kGW;   // i-groups (UREG layout)
-  static_assert(!UREG || IC % kGW == 0, "chunks must hold whole i-groups");
+  using F = Fem<T, NI, NJ, NR, NX, MPG, IC, EW, FAST>;
   static_assert(FAST || WPB == 1, "partial tiles run one wave per block");
   __shared__ T Xall[WPB * F::kRows * kPitch];
   const int wave = WPB > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / kTile) : 0;
@@ -447,16 +442,20 @@ __global__ void __launch_bounds__(kTile * WPB)
       nxt.tile += (int64_t)gridDim.x * WPB;
     }
 
-    // ---- u into registers (several chunks) ----------------------------------
-    T ur[UREG ? NJ : 1];
-    if constexpr (UREG) {
+    // ---- u into registers (chunked shapes); X is then free for outputs ----
+    constexpr bool NAT = F::kChunks > 1;
+    T ur[NAT ? NJ : 1];
+    if constexpr (NAT) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) ur[j] = X[j * kPitch + lane];
       __syncthreads();
     }
 
-    const T *__restrict__ S = Spack + (int64_t)cur.g * NR * NJ * (UREG ? kNG * kGW : NI);
-    (void)kNG;
+    // S: chunked shapes read it in its natural [r][i][j] layout (the caller's
+    // buffer when dense, else the packed copy); the others read the packed
+    // [r][j][i] copy.
+    const T *__restrict__ S = (NAT && G.s_dense) ? (const T *)G.S
+                                                 : Spack + (int64_t)cur.g * NR * NI * NJ;
     bool o_fast = full;
     if constexpr (!FAST) {
 #pragma unroll
@@ -530,38 +529,53 @@ __global__ void __launch_bounds__(kTile * WPB)
         }
       }
     };
-    if constexpr (UREG) {
-      // Several equal chunks of IC outputs (NI padded to kChunks * IC, the
-      // padded rows of S are zero and the padded outputs are not stored): one
-      // loop body, so nothing is hoisted from one chunk into another.
+    // Stage 1 over chunks of IC outputs (one chunk when T[NR][NI] fits):
+    //   T[r][ic] = sum_j S[r][i0 + ic][j] u[j]
+    // S in its natural [r][i][j] layout: a group of four accumulators walks
+    // four contiguous S rows together, 8 values of each per scalar load, with
+    // u in registers.  Rows past NI (the last chunk's padding) re-read row
+    // NI - 1; their results are never stored.  One loop body for all chunks,
+    // so nothing is hoisted from one chunk into the next.
+    if constexpr (NAT) {
 #pragma unroll 1
-      for (int ch = 0; ch < F::kChunks; ++ch) {
-        const int i0 = ch * IC;
-        lane = fresh_lane();   // per-chunk addresses: nothing hoisted across chunks
-        T t[NR][IC];
+    for (int ch = 0; ch < F::kChunks; ++ch) {
+      const int i0 = ch * IC;
+      if (F::kChunks > 1) lane = fresh_lane();
+      T t[NR][IC];
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
+      for (int r = 0; r < NR; ++r)
 #pragma unroll
-          for (int ic = 0; ic < IC; ++ic) t[r][ic] = 0;
-        // S packed [r][i-group][j][kGW]: each scalar load is the kGW values
-        // of one j row that the group's kGW accumulators consume next.
+        for (int ic = 0; ic < IC; ++ic) t[r][ic] = 0;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
+      for (int r = 0; r < NR; ++r) {
 #pragma unroll
-          for (int gi = 0; gi < IC / kGW; ++gi) {
-            const T *__restrict__ Sg =
-                S + (((int64_t)r * kNG + ch * (IC / kGW) + gi) * NJ) * kGW;
+        for (int g4 = 0; g4 < (IC + 3) / 4; ++g4) {
+          const T *__restrict__ rows[4];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j)
-#pragma unroll
-              for (int w = 0; w < kGW; ++w)
-                t[r][gi * kGW + w] = fma(Sg[j * kGW + w], ur[UREG ? j : 0], t[r][gi * kGW + w]);
+          for (int q = 0; q < 4; ++q) {
+            int i = i0 + g4 * 4 + q;
+            i = i < NI ? i : NI - 1;
+            rows[q] = S + ((int64_t)r * NI + i) * NJ;
           }
+#pragma unroll
+          for (int jb = 0; jb < NJ; jb += 8)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int ic = g4 * 4 + q;
+              if (ic < IC) {
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                  if (jb + jj < NJ) t[r][ic] = fma(rows[q][jb + jj], ur[NAT ? jb + jj : 0], t[r][ic]);
+              }
+            }
         }
-        const int ic_n = NI - i0 < IC ? NI - i0 : IC;
-        stage2_store(t, i0, ic_n);
       }
+      const int ic_n = NI - i0 < IC ? NI - i0 : IC;
+      stage2_store(t, i0, ic_n);
+    }
     } else {
+      // One chunk: T[r][i] = sum_j S[r][j][i] u[j] with S packed [r][j][i],
+      // a row of NI wave-uniform values per (r, j), u read from LDS.
       T t[NR][NI];
 #pragma unroll
       for (int r = 0; r < NR; ++r)
@@ -587,59 +601,51 @@ __global__ void __launch_bounds__(kTile * WPB)
   }
 }
 
-// S of every group packed from the caller's strides, either as
-// [group][r][j][i] (u read from LDS) or, with u in registers, as
-// [group][r][i / kGW][j][i % kGW] with i padded to a multiple of kGW (zeros).
+// S packed from the caller's strides into the layout the kernel reads:
+// [group][r][j][i] (one-chunk shapes) or [group][r][i][j] (chunked shapes,
+// only for groups whose S is not already dense in that order).
 struct PackArgs {
   const void *S[BES_FEM_MAX_GROUPS];
   int64_t sr[BES_FEM_MAX_GROUPS], si[BES_FEM_MAX_GROUPS], sj[BES_FEM_MAX_GROUPS];
   int n_groups, NR, NI, NJ;
-  int nip;   // > 0: grouped layout with i padded to nip
+  int transposed;   // 1: [group][r][j][i]; 0: [group][r][i][j]
 };
 
 template <typename T>
 __global__ void __launch_bounds__(256) pack_s_kernel(const PackArgs a, T *__restrict__ dst) {
-  const bool grouped = a.nip > 0;
-  const int nip = grouped ? a.nip : a.NI;
-  const int per = a.NR * a.NJ * nip;
+  const int per = a.NR * a.NI * a.NJ;
   const int total = per * a.n_groups;
   for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < total; f += gridDim.x * blockDim.x) {
     const int g = f / per;
     int rem = f - g * per;
-    const int r = rem / (a.NJ * nip);
-    rem -= r * a.NJ * nip;
+    const int r = rem / (a.NI * a.NJ);
+    rem -= r * a.NI * a.NJ;
     int i, j;
-    if (grouped) {
-      const int gi = rem / (a.NJ * kGW);
-      rem -= gi * a.NJ * kGW;
-      j = rem / kGW;
-      i = gi * kGW + (rem - j * kGW);
+    if (a.transposed) {
+      j = rem / a.NI;
+      i = rem - j * a.NI;
     } else {
-      j = rem / nip;
-      i = rem - j * nip;
+      i = rem / a.NJ;
+      j = rem - i * a.NJ;
     }
-    dst[f] = i < a.NI ? ((const T *)a.S[g])[r * a.sr[g] + i * a.si[g] + j * a.sj[g]] : (T)0;
+    if (a.S[g]) dst[f] = ((const T *)a.S[g])[r * a.sr[g] + i * a.si[g] + j * a.sj[g]];
   }
 }
 
-// i-chunk of the stage-1 accumulator: the whole row when T[NR][NI] fits in
-// 120 VGPRs, else chunks of whole kGW-groups within 48 VGPRs (u then lives in
-// registers and S is packed grouped, padded to a whole number of chunks).
+// i-chunk of the stage-1 accumulator: the whole T[NR][NI] when it fits in
+// 120 VGPRs (u then stays in LDS), else as few equal chunks as keep each
+// within 64 VGPRs (u and G are in registers too).
 template <typename T, int NI, int NR>
-constexpr int kIC = (NR * NI * (int)sizeof(T) / 4 <= 120)
-                        ? NI
-                        : (48 * 4 / ((int)sizeof(T) * NR)) / kGW * kGW;
+constexpr int kChunksOf = (NR * NI * (int)sizeof(T) / 4 <= 120)
+                              ? 1
+                              : (NR * NI * (int)sizeof(T) / 4 + 63) / 64;
+template <typename T, int NI, int NR>
+constexpr int kIC = (NI + kChunksOf<T, NI, NR> - 1) / kChunksOf<T, NI, NR>;
 
-// Padded i extent of the packed S for these extents (0: ungrouped layout).
-int grouped_nip(bool f64, int NI, int NR) {
-#define BES_NIP_CASE(ni, nj, nr, nx)                                                  \
-  if (NI == ni && NR == nr) {                                                        \
-    const int ic = f64 ? kIC<double, ni, nr> : kIC<float, ni, nr>;                   \
-    return ic < ni ? (ni + ic - 1) / ic * ic : 0;                                    \
-  }
-  BES_FEM_SHAPES(BES_NIP_CASE)
-#undef BES_NIP_CASE
-  return 0;
+// Stage-1 chunks of a shape (1: T in registers whole, u read from LDS).
+int chunks_of(bool f64, int NI, int NR) {
+  return f64 ? (NR * NI * 2 <= 120 ? 1 : (NR * NI * 2 + 63) / 64)
+             : (NR * NI <= 120 ? 1 : (NR * NI + 63) / 64);
 }
 
 // Waves per block: one, unless S (read through the scalar data cache by every
@@ -652,7 +658,6 @@ template <typename T, int NI, int NJ, int NR, int NX>
 hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, bool fast, dim3 grid,
                         hipStream_t s) {
   constexpr int IC = kIC<T, NI, NR>;
-  constexpr bool UREG = IC < NI;
   constexpr int WPB = kWPB<T, NI, NJ, NR>;
   // FAST launches of multi-wave blocks cover WPB tiles per block.
   dim3 g = grid;
@@ -660,7 +665,7 @@ hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, bool
   // Functional (element-wise) operands get their own instantiations, so the
   // plain kernels carry no prologue code; those keep one member per group.
 #define BES_FEM_LAUNCH(MPG, EW, FAST)                                                            \
-  hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, MPG, IC, EW, FAST, UREG,              \
+  hipLaunchKernelGGL((fem_stream_kernel<T, NI, NJ, NR, NX, MPG, IC, EW, FAST,                    \
                                         FAST ? WPB : 1>),                                        \
                      FAST ? g : grid, dim3(kTile * (FAST ? WPB : 1)), 0, s, a, spack)
   if (ew) {
@@ -723,8 +728,7 @@ int device_cu_count() {
 }
 
 size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR) {
-  const int nip = std::max(NI, grouped_nip(f64, NI, NR));
-  return (size_t)BES_FEM_MAX_GROUPS * NR * NJ * nip * (f64 ? 8 : 4);
+  return (size_t)BES_FEM_MAX_GROUPS * NR * NJ * NI * (f64 ? 8 : 4);
 }
 
 hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
@@ -760,27 +764,39 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
     FemMember &M = c.mem[m];
     M.o_dense = (M.oe == (int64_t)NX * NI && (NX == 1 || M.ox == NI) && M.oi == 1) ? 1 : 0;
   }
-  // Pack S of every chunk (chunks of one group repeat its S).
+  // S is read in place when it is dense [r][i][j]; other layouts are packed
+  // into that layout first (one small kernel, only when needed).
   PackArgs pk;
   pk.n_groups = c.n_groups;
   pk.NR = NR;
   pk.NI = NI;
   pk.NJ = NJ;
+  bool need_pack = false;
+  pk.transposed = chunks_of(f64, NI, NR) == 1 ? 1 : 0;
   for (int k = 0; k < c.n_groups; ++k) {
-    pk.S[k] = c.grp[k].S;
-    pk.sr[k] = c.grp[k].ss[0];
-    pk.si[k] = c.grp[k].ss[1];
-    pk.sj[k] = c.grp[k].ss[2];
+    FemGroup &G = c.grp[k];
+    const bool dense = !pk.transposed && G.ss[2] == 1 && (NI == 1 || G.ss[1] == NJ) &&
+                       (NR == 1 || G.ss[0] == (int64_t)NI * NJ);
+    G.s_dense = dense ? 1 : 0;
+    pk.S[k] = dense ? nullptr : G.S;
+    pk.sr[k] = G.ss[0];
+    pk.si[k] = G.ss[1];
+    pk.sj[k] = G.ss[2];
+    need_pack |= !dense;
   }
-  pk.nip = grouped_nip(f64, NI, NR);
-  const int pack_total = NR * NJ * (pk.nip > 0 ? pk.nip : NI) * c.n_groups;
-  dim3 pgrid((pack_total + 255) / 256);
-  if (f64)
-    hipLaunchKernelGGL(pack_s_kernel<double>, pgrid, dim3(256), 0, stream, pk, (double *)workspace);
-  else
-    hipLaunchKernelGGL(pack_s_kernel<float>, pgrid, dim3(256), 0, stream, pk, (float *)workspace);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (need_pack) {
+    const int pack_total = NR * NI * NJ * c.n_groups;
+    dim3 pgrid((pack_total + 255) / 256);
+    if (f64)
+      hipLaunchKernelGGL(pack_s_kernel<double>, pgrid, dim3(256), 0, stream, pk,
+                         (double *)workspace);
+    else
+      hipLaunchKernelGGL(pack_s_kernel<float>, pgrid, dim3(256), 0, stream, pk,
+                         (float *)workspace);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (blocks_per_cu < 1) blocks_per_cu = 1;
   (void)prefetch;
   // Full dense tiles go to the straight-line FAST instantiation; the last
