@@ -107,8 +107,8 @@ enum bes_template {
   BES_T_AUTO = 0,        /* let the planner pick */
   BES_T_FEM_STREAM = 1,  /* per-element operands streamed from HBM, small
                             shared operand uniform per wave; p[0] = elements
-                            per tile (64: one wave), p[1] = resident
-                            one-wave blocks per CU (1..32) */
+                            per tile (64: one wave), p[1] = grid size in
+                            one-wave blocks per compute unit (1..64) */
   BES_T_GENERIC = 2,     /* any batched einsum; p[0] = outputs per tile,
                             p[1] = lanes per output (1,2,4,...,64) */
   BES_T_MFMA = 3         /* dense contraction on MFMA (FP32 in, FP32 acc);
@@ -210,6 +210,15 @@ int bes_ctx_stats(const bes_ctx *ctx, int64_t *hits, int64_t *misses);
  * Asynchronous; returns BES_E_HIP if the launch could not be enqueued. */
 int bes_launch(const bes_plan *plan, const void *const *src_ptrs,
                void *const *out_ptrs, void *hip_stream);
+
+/* Profiling hook.  With both events non-NULL (hipEvent_t handles the caller
+ * owns and keeps alive), every later bes_launch of the plan records
+ * start_event on its stream right before the plan's evaluation kernel(s) and
+ * stop_event right after them; a re-layout of the shared operand that the
+ * FEM-stream template may enqueue first is outside the pair.  NULL, NULL
+ * turns it off.  BES_E_INVALID if only one event is given.  Makes no HIP
+ * call itself. */
+int bes_plan_set_timing(bes_plan *plan, void *start_event, void *stop_event);
 
 /* Persistent batched launch of many plans (one kernel over a device work list
  * of (plan, member, tile) items, captured once in a hipGraph).

@@ -183,6 +183,18 @@ class Plan:
     def launch_ptrs(self, src_ptrs: Sequence[int], out_ptrs: Sequence[int], stream: int = 0):
         capi.bes_launch(self.h, list(src_ptrs), list(out_ptrs), stream)
 
+    def set_timing(self, start_event=None, stop_event=None):
+        """Record torch.cuda.Event ``start_event`` / ``stop_event`` around the
+        plan's evaluation kernel(s) on every later launch (None, None: off).
+        The events must stay alive while they are in use."""
+        import torch
+        for ev in (start_event, stop_event):
+            if ev is not None and not ev.cuda_event:   # torch creates events lazily
+                ev.record(torch.cuda.current_stream())
+        h0 = start_event.cuda_event if start_event is not None else 0
+        h1 = stop_event.cuda_event if stop_event is not None else 0
+        capi.bes_plan_set_timing(self.h, h0, h1)
+
     def adjoint(self, pos: int) -> "Plan":
         h, n_out, status = capi.bes_adjoint(self.ctx.h, self.h, pos)
         return Plan(self.ctx, h, None, None, None, None, status, n_out)

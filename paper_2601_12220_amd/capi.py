@@ -103,6 +103,7 @@ def load():
         "bes_db_record": ([P, cp, cp, ctypes.POINTER(bes_config), ctypes.c_double], i32),
         "bes_ctx_stats": ([P, i64p, i64p], i32),
         "bes_launch": ([P, PP, PP, P], i32),
+        "bes_plan_set_timing": ([P, P, P], i32),
         "bes_batch_create": ([P, PP, i32, PP], i32),
         "bes_batch_launch": ([P, ctypes.POINTER(PP), ctypes.POINTER(PP), P], i32),
         "bes_batch_destroy": ([P], None),
@@ -248,6 +249,11 @@ def bes_ctx_stats(ctx):
 
 def _ptrs(ptrs):
     return (ctypes.c_void_p * max(1, len(ptrs)))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+
+
+def bes_plan_set_timing(h, start_event: int, stop_event: int) -> None:
+    check(load().bes_plan_set_timing(h, ctypes.c_void_p(start_event or None),
+                                     ctypes.c_void_p(stop_event or None)), "bes_plan_set_timing")
 
 
 def bes_launch(h, src_ptrs, out_ptrs, stream: int = 0) -> None:

@@ -263,6 +263,15 @@ int bes_ctx_stats(const bes_ctx *ctx, int64_t *hits, int64_t *misses) {
   return BES_OK;
 }
 
+int bes_plan_set_timing(bes_plan *plan, void *start_event, void *stop_event) {
+  if (!plan) return fail(BES_E_INVALID, "NULL plan");
+  if ((start_event == nullptr) != (stop_event == nullptr))
+    return fail(BES_E_INVALID, "give both events or neither");
+  plan->p.time_start = start_event;
+  plan->p.time_stop = stop_event;
+  return BES_OK;
+}
+
 int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *out_ptrs,
                void *hip_stream) {
   if (!plan || !src_ptrs || !out_ptrs) return fail(BES_E_INVALID, "NULL argument");
@@ -305,7 +314,8 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
         p.fem_ws_device = dev;
       }
       e = bes::launch_fem(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, a, p.fem_ws, p.cfg.p[1],
-                          p.cfg.p[2] != 0, stream);
+                          p.cfg.p[2] != 0, stream, (hipEvent_t)p.time_start,
+                          (hipEvent_t)p.time_stop);
       if (e != hipSuccess) return hip_fail(e, "FEM-stream launch");
       return BES_OK;
     }
@@ -313,7 +323,12 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
       MfmaArgs a;
       int rc = bes::bind_mfma(p, src.data(), out_ptrs, a, err);
       if (rc) return fail(rc, err);
+      if (p.time_start && (e = hipEventRecord((hipEvent_t)p.time_start, stream)) != hipSuccess)
+        return hip_fail(e, "timing event");
       e = bes::launch_mfma(a, p.cfg.p[0], p.cfg.p[1], stream);
+      if (e == hipSuccess && p.time_stop &&
+          (e = hipEventRecord((hipEvent_t)p.time_stop, stream)) != hipSuccess)
+        return hip_fail(e, "timing event");
       if (e == hipSuccess) return BES_OK;
       if (e != hipErrorInvalidValue) return hip_fail(e, "MFMA launch");
       // unaligned rows for the vector tile loads: evaluate with the generic
@@ -342,9 +357,15 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
       }
       GenPtrs ptrs;
       bes::bind_generic_ptrs(p, src.data(), out_ptrs, ptrs);
+      if (p.time_start && (e = hipEventRecord((hipEvent_t)p.time_start, stream)) != hipSuccess) {
+        delete g;
+        return hip_fail(e, "timing event");
+      }
       e = bes::launch_generic(f64, (const GenEinsum *)p.gen_dev, *g, ptrs, stream);
       delete g;
       if (e != hipSuccess) return hip_fail(e, "generic launch");
+      if (p.time_stop && (e = hipEventRecord((hipEvent_t)p.time_stop, stream)) != hipSuccess)
+        return hip_fail(e, "timing event");
       return BES_OK;
     }
     default:

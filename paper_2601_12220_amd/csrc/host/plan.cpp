@@ -316,9 +316,18 @@ bes_config default_config(const Plan &p) {
     c.p[0] = 64;   // elements per tile (one wave)
     c.p[1] = 32;   // one-wave blocks per CU in the grid (measured best)
   } else if (template_supported(p, BES_T_GENERIC)) {
+    // Lanes per output grow with the contraction length (about 64 products
+    // per lane), so that long contractions are split across a wavefront.
+    int64_t con = 1;
+    for (int c2 = 0; c2 < (int)p.canon.form.extent.size(); ++c2)
+      if (std::find(p.canon.form.out.begin(), p.canon.form.out.end(), c2) ==
+          p.canon.form.out.end())
+        con *= p.canon.form.extent[c2];
+    int lanes = 1;
+    while (lanes < 64 && (int64_t)lanes * 64 < con) lanes *= 2;
     c.template_id = BES_T_GENERIC;
     c.p[0] = 256;
-    c.p[1] = 1;
+    c.p[1] = lanes;
   } else {
     c.template_id = BES_T_AUTO;  // nothing evaluates this plan
   }

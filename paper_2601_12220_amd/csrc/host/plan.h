@@ -61,6 +61,10 @@ struct Plan {
   mutable void *gen_dev = nullptr;
   mutable int gen_dev_device = -1;
   mutable bes_config gen_dev_cfg{};
+  // Profiling hook (bes_plan_set_timing): events recorded around the main
+  // evaluation kernel(s) of every launch; caller-owned hipEvent_t handles.
+  void *time_start = nullptr;
+  void *time_stop = nullptr;
 };
 
 // Analyse a registered spec: canonicalize, fill roles, default config.

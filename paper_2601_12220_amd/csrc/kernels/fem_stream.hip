@@ -732,7 +732,8 @@ size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR) {
 }
 
 hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
-                      int blocks_per_cu, bool prefetch, hipStream_t stream) {
+                      int blocks_per_cu, bool prefetch, hipStream_t stream, hipEvent_t ev_start,
+                      hipEvent_t ev_stop) {
   if (a.E <= 0) return hipSuccess;
   if (!workspace) return hipErrorInvalidValue;
   int maxm = 0;
@@ -838,11 +839,13 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
 #undef BES_FEM_DISPATCH
     return hipErrorInvalidValue;
   };
+  if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
   if (full_tiles > 0) {
     e = launch(true, 0, full_tiles);
     if (e != hipSuccess) return e;
   }
-  if (full_tiles < tiles) return launch(false, full_tiles, tiles);
+  if (full_tiles < tiles && (e = launch(false, full_tiles, tiles)) != hipSuccess) return e;
+  if (ev_stop && (e = hipEventRecord(ev_stop, stream)) != hipSuccess) return e;
   return hipSuccess;
 }
 

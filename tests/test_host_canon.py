@@ -448,3 +448,26 @@ def test_adjoint_of_dense_pair(ctx):
     assert len(rows) == 2 and len({r[0] for r in rows} & {r[1] for r in rows} | set(rows[0]) & set(rows[1])) >= 1
     shared = set(rows[0]) & set(rows[1])
     assert len(shared) == 1
+
+
+def test_timing_hook_argument_checks(ctx):
+    """bes_plan_set_timing makes no HIP call: both-or-neither is checked on
+    the host, and NULL, NULL switches the hook off."""
+    import ctypes
+    w = workloads.config1()
+    p = ctx.register(w.notation, w.table, w.operands)
+    lib = capi.load()
+    assert lib.bes_plan_set_timing(p.h, ctypes.c_void_p(1), None) == capi.BES_E_INVALID
+    assert lib.bes_plan_set_timing(p.h, None, ctypes.c_void_p(1)) == capi.BES_E_INVALID
+    assert lib.bes_plan_set_timing(None, None, None) == capi.BES_E_INVALID
+    assert lib.bes_plan_set_timing(p.h, None, None) == capi.BES_OK
+
+
+def test_generic_default_lanes_follow_the_contraction(ctx):
+    """Default generic config: about 64 products per lane, at most 64 lanes."""
+    for k, lanes in ((8, 1), (512, 8), (1 << 14, 64)):
+        ops = {"A": (make_operand((4, k), "float32"), ["A"]),
+               "B": (make_operand((k,), "float32"), ["B"])}
+        p = ctx.register("ab,b->a", [["A", "B"]], ops)
+        assert p.template == "generic"
+        assert p.config.p[1] == lanes, (k, p.config.p[1])
