@@ -682,6 +682,211 @@ hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, bool
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// FP64 matrix-core variant for shapes whose S outgrows the scalar data cache
+// (P4: S = 3 x 35 x 35 doubles).  Stage 1 of a tile is a dense contraction,
+//   T[e, (r, i)] = sum_j u[e, j] S[r, i, j]      (64 x 35 times 35 x 105),
+// run as v_mfma_f64_16x16x4f64 blocks: M = 16 elements, N = 16 values of i for
+// one r, K = 4 values of j.  S is staged once per block in LDS in fragment
+// order (B operand, one double per lane, so every LDS read feeds 16
+// elements), u of the tile in registers (A operand); the waves of a block
+// share S and nothing else, and run unsynchronized.  Stage 2 runs in the
+// accumulator layout -- lane l, item v of block mb holds element
+// 16 mb + 4 v + l / 16 and i = 16 ib + l % 16 -- reading the per-element G from
+// LDS, and each store writes four 16-value runs of one output row.
+// Operand layouts (checked on gfx950): A[i][k] in lane i + 16 k,
+// B[k][j] in lane j + 16 k, D[i][j] item v of lane l with i = 4 v + l / 16,
+// j = l % 16.
+// ---------------------------------------------------------------------------
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// True for the FP64 shapes that take the matrix-core variant.
+constexpr bool mfma_shape(int NI, int NJ, int NR) {
+  return NI >= 16 && NJ >= 4 && NR * NI * NJ * 8 > 12 * 1024;
+}
+
+constexpr int kMW = 8;       // waves per block (one block per CU, 2 per SIMD)
+
+// Ordering of one wave's own LDS accesses (its staging regions are private):
+// LDS executes a wave's instructions in order, so only the compiler must be
+// kept from moving accesses across this point; waves never wait for each
+// other, so their load and matrix phases interleave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+constexpr int kUPass = 12;   // u rows staged per pass (3 K-blocks)
+
+template <int NI, int NJ, int NR, int NX>
+struct MfmaFem {
+  static constexpr int kIB = (NI + 15) / 16;           // 16-wide i blocks
+  static constexpr int kKB = (NJ + 3) / 4;             // 4-deep j blocks
+  static constexpr int kFrags = NR * kIB * kKB;        // B fragments of S
+  static constexpr int kPasses = (kKB * 4 + kUPass - 1) / kUPass;
+  static constexpr int kGRows = NX * NR > kMaxRow ? NX * NR : kMaxRow;
+};
+
+template <int NI, int NJ, int NR, int NX, bool EW>
+__global__ void __launch_bounds__(kTile * kMW) __attribute__((amdgpu_waves_per_eu(2)))
+    fem_mfma_kernel(const FemArgs a) {
+  using M = MfmaFem<NI, NJ, NR, NX>;
+  using D = Dense<double, NJ>;
+  __shared__ double Sf[M::kFrags * kTile];
+  __shared__ double Xall[kMW * kUPass * kPitch];
+  __shared__ double Jall[kMW * M::kGRows * kPitch];
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kTile);
+  double *const X = Xall + wave * kUPass * kPitch;
+  double *const Jb = Jall + wave * M::kGRows * kPitch;
+
+  // S of every group (the launcher checks they are one buffer) as fragments:
+  // fragment (r, ib, kb), lane l = S[r][16 ib + l % 16][4 kb + l / 16].
+  {
+    const FemGroup &G0 = a.grp[0];
+    const double *__restrict__ S = (const double *)G0.S;
+    for (int f = threadIdx.x; f < M::kFrags * kTile; f += kTile * kMW) {
+      const int frag = f / kTile, l = f - frag * kTile;
+      const int r = frag / (M::kIB * M::kKB), rem = frag - r * (M::kIB * M::kKB);
+      const int ib = rem / M::kKB, kb = rem - ib * M::kKB;
+      const int i = 16 * ib + l % 16, j = 4 * kb + l / 16;
+      Sf[f] = (i < NI && j < NJ) ? S[r * G0.ss[0] + i * G0.ss[1] + j * G0.ss[2]] : 0.0;
+    }
+    __syncthreads();
+  }
+
+  for (int64_t base = a.tile0 + (int64_t)blockIdx.x * kMW; base < a.tile1;
+       base += (int64_t)gridDim.x * kMW) {
+    const int64_t mine = base + wave;
+    const bool live = mine < a.tile1;          // idle waves repeat the last tile
+    const int64_t e0 = (live ? mine : a.tile1 - 1) * kTile;
+    for (int g = 0; g < a.n_groups; ++g) {
+      int lane = fresh_lane();
+      const FemGroup &G = a.grp[g];
+      // ---- raw loads: the shared G row (first group of the tile), U ------
+      double rg[kMaxRow];
+      const int grow = a.grp[0].g_row;
+      if (g == 0) {
+        const FemSrc &s0 = a.mem[0].g;
+        const double *__restrict__ pb = (const double *)s0.p0 + a.grp[0].g_off + e0 * s0.s0[0];
+        load_block<double, kMaxRow>(rg, pb, false, (int)s0.s0[0], 1, grow, lane);
+      }
+      double ru[D::kLen], rw[EW ? D::kLen : 1];
+      load_dense<double, NJ>(ru, (const double *)G.u.p0 + G.u.off0 + e0 * NJ, lane);
+      if constexpr (EW) {
+        if (G.u.kind == FEM_SRC_ELEMENTWISE && G.u.p1) {
+          load_dense<double, NJ>(rw, (const double *)G.u.p1 + G.u.off1 + e0 * NJ, lane);
+        } else {
+#pragma unroll
+          for (int k = 0; k < D::kLen; ++k) rw[k] = 0.0;
+        }
+      }
+      // ---- G of this lane's element into Jb[x * NR + r][element] ---------
+      if (g == 0) {
+        put_block<double, kMaxRow>(X, rg, lane);
+        wave_sync();
+        double gm[NX][NR];
+        g_from_row<double, NX, NR>(X, a.mem[0].g, lane, gm);
+#pragma unroll
+        for (int x = 0; x < NX; ++x)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) Jb[(x * NR + r) * kPitch + lane] = gm[x][r];
+        wave_sync();
+      }
+      // ---- prologue, then u in passes of kUPass rows into A fragments -------
+      if constexpr (EW) {
+        if (G.u.kind == FEM_SRC_ELEMENTWISE) {
+          const double alpha = G.u.alpha, beta = G.u.beta;
+          const int op = G.u.op;
+#pragma unroll
+          for (int k = 0; k < D::kLen; ++k) ru[k] = alpha * apply_op<double>(op, ru[k]) + beta + rw[k];
+        }
+      }
+      double af[4][M::kKB];
+#pragma unroll
+      for (int p = 0; p < M::kPasses; ++p) {
+#pragma unroll
+        for (int t = 0; t < D::kVT; ++t)
+#pragma unroll
+          for (int sv = 0; sv < D::kV; ++sv) {
+            const int f = D::kV * (lane + kTile * t) + sv;
+            const int el = f / NJ, c = f - el * NJ;
+            if (f < NJ * kTile && c >= p * kUPass && c < (p + 1) * kUPass)
+              X[(c - p * kUPass) * kPitch + el] = ru[t * D::kV + sv];
+          }
+        wave_sync();
+#pragma unroll
+        for (int kl = 0; kl < kUPass / 4; ++kl) {
+          const int kb = p * (kUPass / 4) + kl;
+          if (kb < M::kKB) {
+            const int j = 4 * kb + lane / 16;
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb)
+              af[mb][kb] = j < NJ ? X[(4 * kl + lane / 16) * kPitch + 16 * mb + lane % 16] : 0.0;
+          }
+        }
+        wave_sync();
+      }
+      // ---- stage 1 on the matrix cores, stage 2 in the accumulator layout --
+      // One 16-element block at a time through every i-block, so that the
+      // block's output rows (contiguous) are completed within a short span
+      // and leave L2 as whole lines.
+      double *__restrict__ outp = (double *)a.mem[G.m0].out;   // one member per group
+#pragma unroll 1
+      for (int mb = 0; mb < 4; ++mb) {
+        lane = fresh_lane();
+        d4v acc[NR][M::kIB];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int ib = 0; ib < M::kIB; ++ib) acc[r][ib] = d4v{0.0, 0.0, 0.0, 0.0};
+        double am[M::kKB];
+#pragma unroll
+        for (int kb = 0; kb < M::kKB; ++kb) am[kb] = mb == 0 ? af[0][kb] : mb == 1 ? af[1][kb]
+                                                  : mb == 2 ? af[2][kb] : af[3][kb];
+#pragma unroll
+        for (int kb = 0; kb < M::kKB; ++kb)
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int ib = 0; ib < M::kIB; ++ib) {
+              const double b = Sf[((r * M::kIB + ib) * M::kKB + kb) * kTile + lane];
+              acc[r][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[kb], b, acc[r][ib], 0, 0, 0);
+            }
+#pragma unroll
+        for (int ib = 0; ib < M::kIB; ++ib) {
+          const int i = 16 * ib + lane % 16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int el = 16 * mb + 4 * v + lane / 16;
+#pragma unroll
+            for (int x = 0; x < NX; ++x) {
+              double o = 0.0;
+#pragma unroll
+              for (int r = 0; r < NR; ++r) o = fma(Jb[(x * NR + r) * kPitch + el], acc[r][ib][v], o);
+              if (live && i < NI) __builtin_nontemporal_store(o, &outp[(e0 + el) * (NX * NI) + x * NI + i]);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int NI, int NJ, int NR, int NX>
+hipError_t launch_mfma_shape(const FemArgs &a, bool ew, int grid, hipStream_t s) {
+  if constexpr (mfma_shape(NI, NJ, NR)) {
+    if (ew)
+      hipLaunchKernelGGL((fem_mfma_kernel<NI, NJ, NR, NX, true>), dim3(grid), dim3(kTile * kMW), 0,
+                         s, a);
+    else
+      hipLaunchKernelGGL((fem_mfma_kernel<NI, NJ, NR, NX, false>), dim3(grid), dim3(kTile * kMW), 0,
+                         s, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 // Split groups with more than `mpg` members into several groups that share
 // S and U (T is then recomputed per chunk).
 FemArgs chunk_groups(const FemArgs &in, int mpg, int *group_of_chunk) {
@@ -839,8 +1044,28 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
 #undef BES_FEM_DISPATCH
     return hipErrorInvalidValue;
   };
+  // Matrix-core variant: FP64, large S shared by every group, one G shared
+  // by every member through one row (or none), full dense tiles.
+  bool use_mfma = f64 && fast_ok && full_tiles > 0 && mfma_shape(NI, NJ, NR) && c.g_same &&
+                  c.grp[0].g_row > 0 && NX * NR <= kMaxRow;
+  for (int g = 0; g < c.n_groups && use_mfma; ++g) use_mfma = c.grp[g].m1 - c.grp[g].m0 == 1;
+  for (int g = 1; g < c.n_groups && use_mfma; ++g)
+    use_mfma = c.grp[g].S == c.grp[0].S && c.grp[g].ss[0] == c.grp[0].ss[0] &&
+               c.grp[g].ss[1] == c.grp[0].ss[1] && c.grp[g].ss[2] == c.grp[0].ss[2];
   if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
-  if (full_tiles > 0) {
+  if (use_mfma) {
+    FemArgs d = c;
+    d.tile0 = 0;
+    d.tile1 = full_tiles;
+    const int64_t blocks = std::min<int64_t>((full_tiles + kMW - 1) / kMW,
+                                             (int64_t)device_cu_count() * std::max(1, blocks_per_cu / kMW));
+#define BES_FEM_MFMA_DISPATCH(ni, nj, nr, nx)                                                   \
+    if (NI == ni && NJ == nj && NR == nr && NX == nx) e = launch_mfma_shape<ni, nj, nr, nx>(d, ew, (int)blocks, stream);
+    e = hipErrorInvalidValue;
+    BES_FEM_SHAPES(BES_FEM_MFMA_DISPATCH)
+#undef BES_FEM_MFMA_DISPATCH
+    if (e != hipSuccess) return e;
+  } else if (full_tiles > 0) {
     e = launch(true, 0, full_tiles);
     if (e != hipSuccess) return e;
   }
