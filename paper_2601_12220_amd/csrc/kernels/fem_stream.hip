@@ -863,7 +863,10 @@ __global__ void __launch_bounds__(kTile * kMW) __attribute__((amdgpu_waves_per_e
               double o = 0.0;
 #pragma unroll
               for (int r = 0; r < NR; ++r) o = fma(Jb[(x * NR + r) * kPitch + el], acc[r][ib][v], o);
-              if (live && i < NI) __builtin_nontemporal_store(o, &outp[(e0 + el) * (NX * NI) + x * NI + i]);
+              // plain store: L2 merges the 16-value runs of neighbouring
+              // stores into whole lines (a streaming hint would send them
+              // to HBM as partial writes)
+              if (live && i < NI) outp[(e0 + el) * (NX * NI) + x * NI + i] = o;
             }
           }
         }
