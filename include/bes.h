@@ -110,7 +110,9 @@ enum bes_template {
                             per tile (64: one wave), p[1] = grid size in
                             one-wave blocks per compute unit (1..64) */
   BES_T_GENERIC = 2,     /* any batched einsum; p[0] = outputs per tile,
-                            p[1] = lanes per output (1,2,4,...,64) */
+                            p[1] = lanes per output (1,2,4,...,64),
+                            p[2] = chunks of the shared contracted index
+                            space per output (0 or 1: none; up to 64) */
   BES_T_MFMA = 3         /* dense contraction on MFMA (FP32 in, FP32 acc);
                             p[0] = tile M, p[1] = tile N, p[2] = split */
 };

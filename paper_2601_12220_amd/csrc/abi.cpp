@@ -46,6 +46,7 @@ struct bes_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool use_graph = true;
+  bool any_split = false;
 };
 
 namespace {
@@ -427,17 +428,32 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
     }
     B->plans.push_back(&p);
     const GenEinsum &g = table[k];
+    if (g.split > 1) B->any_split = true;
+    // Work per output of the factored evaluation: the shared rows times the
+    // exclusive sums of the operands that depend on them, plus the others.
+    double per = 0.0, once = 0.0;
+    for (int op = 0; op < g.n_ops; ++op) {
+      const double ex = (double)std::max<int64_t>(g.ex_size[op], 1);
+      if ((g.row_dep >> op) & 1) per += ex;
+      else once += ex;
+    }
+    const int chunks = std::max(1, g.split);
+    const double per_output =
+        (double)std::max<int64_t>(g.sh_size, 1) * std::max(per, 1.0) / chunks + once;
     for (int s = 0; s < g.n_slots; ++s) {
-      int members = g.slot_m1[s] - g.slot_m0[s];
+      const int members = g.slot_m1[s] - g.slot_m0[s];
       for (int64_t f = 0; f < g.out_size; f += g.tile) {
-        GenItem it;
-        it.einsum = k;
-        it.slot = s;
-        it.first = f;
-        it.count = std::min<int64_t>(g.tile, g.out_size - f);
-        items.push_back(it);
-        cost.push_back((double)it.count * (double)std::max<int64_t>(g.con_size, 1) * members *
-                       g.n_ops);
+        for (int ch = 0; ch < chunks; ++ch) {
+          GenItem it;
+          std::memset(&it, 0, sizeof it);
+          it.einsum = k;
+          it.slot = s;
+          it.first = f;
+          it.count = std::min<int64_t>(g.tile, g.out_size - f);
+          it.chunk = ch;
+          items.push_back(it);
+          cost.push_back((double)it.count * members * per_output);
+        }
       }
     }
   }
@@ -506,7 +522,8 @@ int bes_batch_launch(bes_batch *B, const void *const *const *src_ptrs, void *con
     bool ok = hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       hipError_t le = bes::launch_persistent(B->f64, B->d_table, B->d_ptrs, B->d_items, B->n_items,
-                                             B->d_counters, B->grid, B->capture_stream);
+                                             B->d_counters, B->grid, B->capture_stream,
+                                             (int)B->plans.size(), B->any_split);
       hipGraph_t g = nullptr;
       hipError_t ce = hipStreamEndCapture(B->capture_stream, &g);
       ok = le == hipSuccess && ce == hipSuccess && g;
@@ -528,7 +545,7 @@ int bes_batch_launch(bes_batch *B, const void *const *const *src_ptrs, void *con
     return BES_OK;
   }
   e = bes::launch_persistent(B->f64, B->d_table, B->d_ptrs, B->d_items, B->n_items, B->d_counters,
-                             B->grid, stream);
+                             B->grid, stream, (int)B->plans.size(), B->any_split);
   if (e != hipSuccess) return hip_fail(e, "persistent launch");
   return BES_OK;
 }

@@ -93,13 +93,26 @@ typedef struct GenLayout {
   int64_t so1[BES_GEN_MAX_IDX], sc1[BES_GEN_MAX_IDX];  // output / contracted idx
 } GenLayout;
 
+// The contracted indices are ordered: first the n_sh "shared" ones (each in
+// at least two operands), then, for each operand k, the ex_n[k] indices that
+// only operand k carries (positions ex_off[k] ...).  An exclusive index is
+// summed inside its operand before the product is taken,
+//   sum_{shared} prod_k ( sum_{exclusive of k} M(A^k)[...] ),
+// the same value as Eq. (1) in a factored order; an operand without shared
+// indices (row_dep bit clear) is summed once per output.
 typedef struct GenEinsum {
   int32_t n_ops, n_out, n_con, b, n_slots;
   int32_t lanes;             // lanes cooperating on one output (1..64)
   int32_t tile;              // outputs per work item
-  int32_t pad;
+  int32_t n_sh;              // shared contracted indices (first in con order)
   int64_t out_ext[BES_GEN_MAX_IDX], con_ext[BES_GEN_MAX_IDX];
   int64_t out_size, con_size;
+  int64_t sh_size;                       // product of the shared extents
+  int32_t ex_off[BES_GEN_MAX_OPS], ex_n[BES_GEN_MAX_OPS];
+  int64_t ex_size[BES_GEN_MAX_OPS];      // product of operand k's exclusive extents
+  int32_t row_dep;                       // bit k: operand k carries a shared index
+  int32_t split;                         // chunks of the shared space per output
+                                         // (> 1: chunks add into zeroed outputs)
   int64_t ostride[BES_GEN_MAX_IDX];
   int32_t layout[BES_GEN_MAX_B][BES_GEN_MAX_OPS];  // layout id per (member, op)
   int32_t slot_of[BES_GEN_MAX_B];                  // member -> output slot
@@ -122,6 +135,8 @@ typedef struct GenItem {
   int32_t slot;
   int64_t first;    // first output element of the tile
   int64_t count;    // outputs in the tile
+  int32_t chunk;    // chunk of the shared contracted space (0..split-1)
+  int32_t pad;
 } GenItem;
 
 // ---------------------------------------------------------------------------

@@ -316,18 +316,40 @@ bes_config default_config(const Plan &p) {
     c.p[0] = 64;   // elements per tile (one wave)
     c.p[1] = 32;   // one-wave blocks per CU in the grid (measured best)
   } else if (template_supported(p, BES_T_GENERIC)) {
-    // Lanes per output grow with the contraction length (about 64 products
-    // per lane), so that long contractions are split across a wavefront.
+    // Lanes per output grow with the shared contraction length (about 64
+    // rows per lane; the generic template splits those rows across lanes and
+    // sums each operand's exclusive indices inside the operand).
+    const CanonEinsum &f = p.canon.form;
     int64_t con = 1;
-    for (int c2 = 0; c2 < (int)p.canon.form.extent.size(); ++c2)
-      if (std::find(p.canon.form.out.begin(), p.canon.form.out.end(), c2) ==
-          p.canon.form.out.end())
-        con *= p.canon.form.extent[c2];
+    bool any_shared = false;
+    for (int c2 = 0; c2 < (int)f.extent.size(); ++c2) {
+      if (std::find(f.out.begin(), f.out.end(), c2) != f.out.end()) continue;
+      int h = 0;
+      for (const auto &l : f.ins) h += std::find(l.begin(), l.end(), c2) != l.end() ? 1 : 0;
+      if (h >= 2) {
+        con *= f.extent[c2];
+        any_shared = true;
+      }
+    }
+    if (!any_shared)   // the largest exclusive set takes the shared place
+      for (const auto &l : f.ins) {
+        int64_t ex = 1;
+        for (int c2 : l)
+          if (std::find(f.out.begin(), f.out.end(), c2) == f.out.end()) ex *= f.extent[c2];
+        con = std::max(con, ex);
+      }
     int lanes = 1;
     while (lanes < 64 && (int64_t)lanes * 64 < con) lanes *= 2;
+    // Few outputs over a long shared contraction: split the shared space
+    // into chunks that add into the zeroed outputs (more work items).
+    int64_t outs = (int64_t)p.n_slots;
+    for (int c2 : f.out) outs *= f.extent[c2];
+    int split = 1;
+    while (split < 64 && outs * split < 4096 && con / (split * 2) >= 1024) split *= 2;
     c.template_id = BES_T_GENERIC;
     c.p[0] = 256;
     c.p[1] = lanes;
+    c.p[2] = split;
   } else {
     c.template_id = BES_T_AUTO;  // nothing evaluates this plan
   }
@@ -512,9 +534,46 @@ int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std:
   g.n_ops = s.n;
   g.b = s.b;
   g.n_out = (int)s.out.size();
+  // Contracted indices: shared ones first, then each operand's exclusive
+  // ones (an index is exclusive when exactly one operand position carries
+  // it, possibly on several axes).
   std::vector<int> con;
+  auto holders = [&](int c) {
+    int h = 0;
+    for (int j = 0; j < s.n; ++j) h += contains(s.ins[j], c) ? 1 : 0;
+    return h;
+  };
   for (int c : s.used_indices())
-    if (!contains(s.out, c)) con.push_back(c);
+    if (!contains(s.out, c) && holders(c) >= 2) con.push_back(c);
+  // Without shared indices, the largest exclusive set takes their place, so
+  // that the lanes and chunks split its sum.
+  int promoted = -1;
+  if (con.empty()) {
+    int64_t best = 1;
+    for (int j = 0; j < s.n; ++j) {
+      int64_t ex = 1;
+      for (int c : s.used_indices())
+        if (!contains(s.out, c) && contains(s.ins[j], c)) ex *= s.extent[c];
+      if (ex > best) {
+        best = ex;
+        promoted = j;
+      }
+    }
+    if (promoted >= 0)
+      for (int c : s.used_indices())
+        if (!contains(s.out, c) && contains(s.ins[promoted], c)) con.push_back(c);
+  }
+  g.n_sh = (int)con.size();
+  g.row_dep = 0;
+  for (int j = 0; j < s.n; ++j) {
+    g.ex_off[j] = (int)con.size();
+    if (j != promoted)
+      for (int c : s.used_indices())
+        if (!contains(s.out, c) && holders(c) == 1 && contains(s.ins[j], c)) con.push_back(c);
+    g.ex_n[j] = (int)con.size() - g.ex_off[j];
+    for (int q = 0; q < g.n_sh; ++q)
+      if (contains(s.ins[j], con[q])) g.row_dep |= 1 << j;
+  }
   g.n_con = (int)con.size();
   g.out_size = 1;
   for (int d = g.n_out - 1; d >= 0; --d) {
@@ -527,8 +586,19 @@ int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std:
     g.con_ext[d] = s.extent[con[d]];
     g.con_size *= g.con_ext[d];
   }
+  g.sh_size = 1;
+  for (int d = 0; d < g.n_sh; ++d) g.sh_size *= g.con_ext[d];
+  for (int j = 0; j < s.n; ++j) {
+    g.ex_size[j] = 1;
+    for (int d = 0; d < g.ex_n[j]; ++d) g.ex_size[j] *= g.con_ext[g.ex_off[j] + d];
+  }
   g.tile = cfg.p[0] > 0 ? cfg.p[0] : 256;
   g.lanes = cfg.p[1] > 0 ? cfg.p[1] : 1;
+  g.split = cfg.p[2] > 0 ? cfg.p[2] : 1;
+  if (g.split > 64) {
+    err = "split of the shared space must be <= 64";
+    return BES_E_INVALID;
+  }
   if (g.lanes > 64 || (g.lanes & (g.lanes - 1))) {
     err = "lanes per output must be a power of two <= 64";
     return BES_E_INVALID;

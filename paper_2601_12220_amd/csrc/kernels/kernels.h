@@ -30,9 +30,11 @@ hipError_t launch_generic(bool f64, const GenEinsum *dev, const GenEinsum &host,
 // Persistent batched launch: blocks pull GenItems off a device counter.
 // `table`/`ptrs` are device arrays indexed by einsum; counters[2] must be zero
 // before the first launch and are left zero by every launch.
+// Einsums with split > 1 get their outputs zeroed by a kernel first
+// (`any_split`), then their chunks add into them.
 hipError_t launch_persistent(bool f64, const GenEinsum *table, const GenPtrs *ptrs,
                              const GenItem *items, int n_items, unsigned *counters,
-                             int grid, hipStream_t stream);
+                             int grid, hipStream_t stream, int n_einsums, bool any_split);
 
 // MFMA dense-contraction template (FP32).
 hipError_t launch_mfma(const MfmaArgs &a, int tile_m, int tile_n, hipStream_t stream);

@@ -28,12 +28,15 @@ def candidates(template_id: int) -> List[Tuple[int, ...]]:
     """Parameter tuples (template id first) the tuner tries for a template.
 
     FEM stream: p[1] = one-wave blocks per compute unit in the grid.
-    Generic:    p[0] = outputs per tile, p[1] = lanes per output.
+    Generic:    p[0] = outputs per tile, p[1] = lanes per output, p[2] = chunks
+                of the shared contracted space (their sums add into the output).
     MFMA:       the single 128 x 128 tile shape the template implements."""
     if template_id == T_FEM_STREAM:
         return [(T_FEM_STREAM, 64, b, 0) for b in (8, 16, 32, 64)]
     if template_id == T_GENERIC:
-        return [(T_GENERIC, tile, lanes) for tile in (64, 256, 1024) for lanes in (1, 4, 16, 64)]
+        # p[2]: chunks of the shared contracted space per output (1: none)
+        return ([(T_GENERIC, tile, lanes, 1) for tile in (64, 256, 1024) for lanes in (1, 4, 16, 64)]
+                + [(T_GENERIC, 256, lanes, split) for lanes in (16, 64) for split in (8, 64)])
     if template_id == T_MFMA:
         return [(T_MFMA, 128, 128)]
     return []

@@ -194,3 +194,33 @@ def test_generic_edge_cases(ctx, nota, shapes):
     p.launch({nm: a.cuda() for nm, a in zip(names, arrs)}, [out])
     torch.cuda.synchronize()
     assert rel_fro(out.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("split", [1, 8, 64])
+def test_generic_factored_and_split(ctx, dtype, split):
+    """Few outputs, long contraction: indices carried by one operand only are
+    summed inside it, the shared space is split into chunks that add into the
+    zeroed outputs (two members, one sharing an argument)."""
+    import oracle
+    from paper_2601_12220_amd import make_operand
+    nota = "vh,fht,ftv,hfv->v"
+    shapes = [(16, 12), (9, 12, 7), (9, 7, 16), (12, 9, 16)]
+    g = torch.Generator().manual_seed(77)
+    names = ["A", "B", "C", "D", "E"]
+    arrs = {nm: torch.randn(*(shapes[k] if k < 4 else shapes[3]), generator=g, dtype=torch.float64)
+            for k, nm in enumerate(names)}
+    if dtype == "float32":
+        arrs = {k: v.float().double() for k, v in arrs.items()}    # FP32-exact inputs
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    ops = {nm: (make_operand(tuple(arrs[nm].shape), dtype), [nm]) for nm in names}
+    table = [["A", "B", "C", "D"], ["A", "B", "C", "E"]]
+    p = ctx.register(nota, table, ops, arg_order=names)
+    p.set_config(capi.BES_T_GENERIC, 4, 16, split)
+    refs = [oracle.einsum(nota, *[arrs[a].numpy() for a in row]) for row in table]
+    outs = [torch.full(refs[0].shape, float("nan"), dtype=tdt, device="cuda") for _ in range(2)]
+    for rep in range(2):          # twice: the zeroing of split outputs must repeat
+        p.launch({k: v.to(tdt).cuda() for k, v in arrs.items()}, outs)
+        torch.cuda.synchronize()
+        for m in range(2):
+            assert rel_fro(outs[m].double().cpu().numpy(), refs[m]) <= TOL[dtype], (split, m, rep)
