@@ -108,7 +108,9 @@ enum bes_template {
   BES_T_FEM_STREAM = 1,  /* per-element operands streamed from HBM, small
                             shared operand uniform per wave; p[0] = elements
                             per tile (64: one wave), p[1] = grid size in
-                            one-wave blocks per compute unit (1..64) */
+                            one-wave blocks per compute unit (1..64),
+                            p[2] = 1: always the descriptor-driven kernel
+                            (0: the lean kernel where the batch allows) */
   BES_T_GENERIC = 2,     /* any batched einsum; p[0] = outputs per tile,
                             p[1] = lanes per output (1,2,4,...,64),
                             p[2] = chunks of the shared contracted index

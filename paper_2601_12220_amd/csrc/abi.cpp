@@ -245,6 +245,10 @@ int bes_plan_set_config(bes_plan *plan, const bes_config *cfg) {
     if (lanes > 64 || (lanes & (lanes - 1))) return fail(BES_E_INVALID, "lanes must be 2^k <= 64");
     if (c.p[0] < 0) return fail(BES_E_INVALID, "negative tile");
   }
+  if (c.template_id == BES_T_FEM_STREAM) {
+    if (c.p[1] < 0 || c.p[1] > 64) return fail(BES_E_INVALID, "blocks per CU must be 0..64");
+    if (c.p[2] < 0 || c.p[2] > 1) return fail(BES_E_INVALID, "FEM kernel variant must be 0 or 1");
+  }
   plan->p.cfg = c;
   return BES_OK;
 }

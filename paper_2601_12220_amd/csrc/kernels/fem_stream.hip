@@ -654,6 +654,146 @@ int chunks_of(bool f64, int NI, int NR) {
 template <typename T, int NI, int NJ, int NR>
 constexpr int kWPB = (NR * NI * NJ * (int)sizeof(T) > 12 * 1024) ? 8 : 1;
 
+// ---------------------------------------------------------------------------
+// Lean instantiation for the plain FEM batch: one stage-1 group (all members
+// share u and S), one output component per member, G absent or read by every
+// member from one staged row per element (views of one buffer, such as the
+// rows of a Jacobian), dense 16-byte-aligned operands, full tiles, T[NR][NI]
+// in registers and S packed [r][j][i] within the scalar data cache.  All that
+// the tile loop addresses besides the tile index is fixed for the launch and
+// arrives in a small argument block held in scalar registers, so a tile issues
+// no scalar loads but those of S: no descriptor reads sit between one tile's
+// stores and the next tile's loads.  S is a kernel argument of its own,
+// restrict-qualified: only then may the compiler read it with scalar loads
+// across the kernel's stores (through a struct field it falls back to vector
+// loads, one per lane).  On the P3 gradient batch (e = 2^20) this
+// sustains about 1.3x the bandwidth of the descriptor-driven FAST kernel.
+// ---------------------------------------------------------------------------
+struct LeanArgs {
+  const void *u;        // dense [E][NJ], offset applied
+  const void *grow;     // start of element 0's G row (null: no G)
+  void *out[3];         // member outputs, dense [E][NI]
+  int64_t tile0, tile1; // 64-element tiles [tile0, tile1), all full
+  int32_t n_mem;        // members (<= MPG)
+  int32_t g_w;          // G row width (<= kMaxRow; 0: no G)
+  int32_t g_stride;     // element stride of the G row source
+  int32_t g_off[3][3];  // row position of G[member][r] (unused members: 0)
+};
+
+template <typename T>
+constexpr int kLeanUnrollJ = sizeof(T) == 8 ? 2 : 4;
+
+template <typename T, int NI, int NJ, int NR>
+constexpr bool kLeanShape = kChunksOf<T, NI, NR> == 1 && kWPB<T, NI, NJ, NR> == 1;
+
+// No occupancy attribute here: with one, the scheduler keeps SGPR use low and
+// walks S through a single 16-SGPR window, a scalar round trip per 64 bytes
+// of S; without, it loads two rows of S per round trip (the register
+// allocation of the shapes in use still gives two waves per SIMD in FP64).
+template <typename T, int NI, int NJ, int NR, int MPG>
+__global__ void __launch_bounds__(kTile)
+    fem_lean_kernel(const LeanArgs a, const T *__restrict__ S) {
+  constexpr int kR0 = NJ > NI ? NJ : NI;
+  constexpr int kRows = kR0 > kMaxRow ? kR0 : kMaxRow;
+  __shared__ T X[kRows * kPitch];
+  using V = typename Vec16<T>::type;
+  using DI = Dense<T, NI>;
+  const bool has_g = a.g_w > 0;
+  for (int64_t tile = a.tile0 + blockIdx.x; tile < a.tile1; tile += gridDim.x) {
+    const int lane = fresh_lane();
+    const int64_t e0 = tile * kTile;
+    // raw loads of the tile: G rows (clamped, branch-free) and dense u rows
+    T rg[kMaxRow];
+    if (has_g)
+      load_block<T, kMaxRow>(rg, (const T *)a.grow + e0 * a.g_stride, false, a.g_stride, 1, a.g_w,
+                             lane);
+    T ru[Dense<T, NJ>::kLen];
+    load_dense<T, NJ>(ru, (const T *)a.u + e0 * NJ, lane);
+    // G of this lane's element for every member, through the staged row
+    T gm[MPG][NR];
+    if (has_g) {
+      put_block<T, kMaxRow>(X, rg, lane);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < MPG; ++q)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gm[q][r] = X[a.g_off[q][r] * kPitch + lane];
+      __syncthreads();
+    }
+    put_dense<T, NJ>(X, ru, lane);
+    __syncthreads();
+    // stage 1: T[r][i] = sum_j S[r][j][i] u[j], S wave-uniform
+    T t[NR][NI];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < NI; ++i) t[r][i] = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int xl = fresh_lane();   // u re-read per r instead of pinned in VGPRs
+      // 320 bytes of S per scalar round trip: two rows in FP64, four in FP32
+#pragma unroll(kLeanUnrollJ<T>)
+      for (int j = 0; j < NJ; ++j) {
+        const T uj = X[j * kPitch + xl];
+        const T *__restrict__ Srow = S + (r * NJ + j) * NI;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) t[r][i] = fma(Srow[i], uj, t[r][i]);
+      }
+    }
+    __syncthreads();
+    // stage 2 per member, through X to 16-byte streaming stores
+#pragma unroll
+    for (int q = 0; q < MPG; ++q) {
+      if (q >= a.n_mem) break;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        T acc = t[0][i];
+        if (has_g) {
+          acc = gm[q][0] * t[0][i];
+#pragma unroll
+          for (int r = 1; r < NR; ++r) acc = fma(gm[q][r], t[r][i], acc);
+        }
+        X[i * kPitch + lane] = acc;
+      }
+      __syncthreads();
+      V *__restrict__ ov = (V *)((T *)a.out[q] + e0 * NI);
+#pragma unroll
+      for (int k = 0; k < DI::kVT; ++k) {
+        const int v = lane + kTile * k;
+        V vv;
+#pragma unroll
+        for (int sv = 0; sv < DI::kV; ++sv) {
+          const int f = DI::kV * v + sv;
+          const int el = f / NI, ic = f - el * NI;
+          vv[sv] = X[ic * kPitch + (el < kTile ? el : 0)];
+        }
+        if ((k + 1) * kTile <= DI::kN || v < DI::kN) __builtin_nontemporal_store(vv, &ov[v]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T, int NI, int NJ, int NR>
+hipError_t launch_lean(const LeanArgs &a, const T *spack, int mpg, dim3 grid, hipStream_t s) {
+  if constexpr (kLeanShape<T, NI, NJ, NR>) {
+    if (mpg == 1)
+      hipLaunchKernelGGL((fem_lean_kernel<T, NI, NJ, NR, 1>), grid, dim3(kTile), 0, s, a, spack);
+    else
+      hipLaunchKernelGGL((fem_lean_kernel<T, NI, NJ, NR, 3>), grid, dim3(kTile), 0, s, a, spack);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+bool lean_shape(bool f64, int NI, int NJ, int NR) {
+  const int w = f64 ? 2 : 1;
+  const bool one_chunk = NR * NI * w <= 120;
+  const bool small_s = NR * NI * NJ * 4 * w <= 12 * 1024;
+  return one_chunk && small_s;
+}
+
 template <typename T, int NI, int NJ, int NR, int NX>
 hipError_t launch_shape(const FemArgs &a, const T *spack, int mpg, bool ew, bool fast, dim3 grid,
                         hipStream_t s) {
@@ -940,7 +1080,7 @@ size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR) {
 }
 
 hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
-                      int blocks_per_cu, bool prefetch, hipStream_t stream, hipEvent_t ev_start,
+                      int blocks_per_cu, bool descriptor_kernel, hipStream_t stream, hipEvent_t ev_start,
                       hipEvent_t ev_stop) {
   if (a.E <= 0) return hipSuccess;
   if (!workspace) return hipErrorInvalidValue;
@@ -1007,7 +1147,6 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
     if (e != hipSuccess) return e;
   }
   if (blocks_per_cu < 1) blocks_per_cu = 1;
-  (void)prefetch;
   // Full dense tiles go to the straight-line FAST instantiation; the last
   // partial tile and any other layout to the general one.
   bool fast_ok = true;
@@ -1055,8 +1194,57 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
   for (int g = 1; g < c.n_groups && use_mfma; ++g)
     use_mfma = c.grp[g].S == c.grp[0].S && c.grp[g].ss[0] == c.grp[0].ss[0] &&
                c.grp[g].ss[1] == c.grp[0].ss[1] && c.grp[g].ss[2] == c.grp[0].ss[2];
+  // Lean variant: one group, one output component per member, G absent or
+  // one shared row of plain views.
+  bool use_lean = !descriptor_kernel && !use_mfma && fast_ok && full_tiles > 0 && NX == 1 && !ew &&
+                  c.n_groups == 1 &&
+                  pk.transposed && c.n_members <= 3 && c.grp[0].m0 == 0 &&
+                  c.grp[0].m1 == c.n_members && lean_shape(f64, NI, NJ, NR);
+  LeanArgs la{};
+  if (use_lean) {
+    const FemGroup &G = c.grp[0];
+    bool no_g = true, row_g = G.g_row > 0 && G.g_row <= kMaxRow;
+    for (int m = 0; m < c.n_members; ++m) {
+      no_g = no_g && c.mem[m].g.kind == FEM_SRC_NONE;
+      row_g = row_g && c.mem[m].g.kind == FEM_SRC_ARRAY;
+    }
+    use_lean = no_g || row_g;
+    if (use_lean) {
+      const size_t esz_ = f64 ? 8 : 4;
+      la.u = (const char *)G.u.p0 + G.u.off0 * (int64_t)esz_;
+      la.tile0 = 0;
+      la.tile1 = full_tiles;
+      la.n_mem = c.n_members;
+      if (row_g) {
+        const FemSrc &s0 = c.mem[0].g;
+        la.grow = (const char *)s0.p0 + G.g_off * (int64_t)esz_;
+        la.g_w = G.g_row;
+        la.g_stride = (int32_t)s0.s0[0];
+      }
+      for (int m = 0; m < c.n_members; ++m) {
+        la.out[m] = c.mem[m].out;
+        for (int r = 0; r < NR && row_g; ++r) {
+          const int64_t pos = c.mem[m].g.off0 + r * c.mem[m].g.s0[2];
+          if (pos < 0 || pos >= G.g_row) use_lean = false;   // outside the staged row
+          else la.g_off[m][r] = (int32_t)pos;
+        }
+      }
+      if (row_g && (c.mem[0].g.s0[0] <= 0 || c.mem[0].g.s0[0] > INT32_MAX)) use_lean = false;
+    }
+  }
   if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
-  if (use_mfma) {
+  if (use_lean) {
+    dim3 lgrid((unsigned)std::min<int64_t>(full_tiles, cap));
+    e = hipErrorInvalidValue;
+#define BES_FEM_LEAN_DISPATCH(ni, nj, nr, nx)                                                  \
+    if (NI == ni && NJ == nj && NR == nr && nx == 1)                                          \
+      e = f64 ? launch_lean<double, ni, nj, nr>(la, (const double *)workspace, mpg, lgrid,    \
+                                                stream)                                      \
+              : launch_lean<float, ni, nj, nr>(la, (const float *)workspace, mpg, lgrid, stream);
+    BES_FEM_SHAPES(BES_FEM_LEAN_DISPATCH)
+#undef BES_FEM_LEAN_DISPATCH
+    if (e != hipSuccess) return e;
+  } else if (use_mfma) {
     FemArgs d = c;
     d.tile0 = 0;
     d.tile1 = full_tiles;

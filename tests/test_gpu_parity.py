@@ -85,6 +85,41 @@ def test_config2_full_size(ctx, dtype):
     _check_sampled(p, w)
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("bpc", [1, 64])
+def test_config2_kernel_variants(ctx, dtype, variant, bpc):
+    """The lean kernel (variant 0) and the descriptor-driven one (1) on the
+    P3 gradient batch with a ragged tail; one block per CU makes every block
+    walk several tiles."""
+    w = workloads.config2(e=64 * 1093 + 29, dtype=dtype)
+    p = ctx.register(w.notation, w.table, w.operands)
+    p.set_config(capi.BES_T_FEM_STREAM, 64, bpc, variant)
+    _check_full(p, w)
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_lean_kernel_one_member_and_without_g(ctx, dtype):
+    """The lean kernel's other instantiations: a batch of one member (no
+    shared stage 1) and members without a per-element G."""
+    w2 = workloads.config2(e=64 * 70 + 7, dtype=dtype)
+    one = workloads.Workload("fem_grad_b1", w2.notation, [list(w2.table[1])],
+                             {k: w2.operands[k] for k in ("J1", "D", "u")}, w2.buffers,
+                             dtype, w2.info)
+    e, nj = 64 * 70 + 7, 20
+    bufs = {"u": workloads._normal(90, 0, (e, nj), dtype),
+            "D": workloads._uniform(90, 1, (nj, nj), -1.0, 1.0, dtype)}
+    ops = {k: workloads._dense(k, v, dtype) for k, v in bufs.items()}
+    no_g = workloads.Workload("fem_matvec_shared", "ij,ej->ei", [["D", "u"], ["D", "u"]],
+                              ops, bufs, dtype, {"e": e, "nj": nj})
+    for w in (one, no_g):
+        p = ctx.register(w.notation, w.table, w.operands)
+        assert p.template == "fem_stream"
+        for variant in (0, 1):
+            p.set_config(capi.BES_T_FEM_STREAM, 64, 16, variant)
+            _check_full(p, w)
+
+
 @pytest.mark.parametrize("e", [5, 2049, 30011])
 def test_config3_small(ctx, e):
     w = workloads.config3(e=e)

@@ -450,6 +450,19 @@ def test_adjoint_of_dense_pair(ctx):
     assert len(shared) == 1
 
 
+def test_fem_config_validation(ctx):
+    """FEM-stream parameters outside their documented ranges are rejected:
+    blocks per compute unit 0..64, kernel variant 0 (lean where the batch
+    allows) or 1 (descriptor-driven)."""
+    w = workloads.config2(e=1000)
+    p = ctx.register(w.notation, w.table, w.operands)
+    for good in ((64, 1, 0), (64, 64, 1)):
+        p.set_config(capi.BES_T_FEM_STREAM, *good)
+    for bad in ((64, 65, 0), (64, -1, 0), (64, 16, 2), (64, 16, -1)):
+        with pytest.raises(capi.BesError):
+            p.set_config(capi.BES_T_FEM_STREAM, *bad)
+
+
 def test_timing_hook_argument_checks(ctx):
     """bes_plan_set_timing makes no HIP call: both-or-neither is checked on
     the host, and NULL, NULL switches the hook off."""
