@@ -157,7 +157,7 @@ def run_fem(w, steps, warmup, tune_first=True):
     tuned = None
     if tune_first:
         with torch.cuda.stream(stream):
-            r = tune.tune(ctx, plan, bufs, outs, stream=stream, reps=10, warmup=2)
+            r = tune.tune(ctx, plan, bufs, outs, stream=stream, reps=30, warmup=3)
         plan = ctx.register(w.notation, w.table, w.operands)     # retrieves the record
         tuned = {"config": list(r.best) if r else None, "retrieved": plan.status}
     src = plan.src_ptrs(bufs)

@@ -108,9 +108,11 @@ enum bes_template {
   BES_T_FEM_STREAM = 1,  /* per-element operands streamed from HBM, small
                             shared operand uniform per wave; p[0] = elements
                             per tile (64: one wave), p[1] = grid size in
-                            one-wave blocks per compute unit (1..64),
-                            p[2] = 1: always the descriptor-driven kernel
-                            (0: the lean kernel where the batch allows) */
+                            blocks per compute unit (1..64), p[2] = kernel
+                            variant: 0 the lean kernel with two waves per
+                            64-element tile where the batch allows it, 2 the
+                            lean kernel with one wave per tile, 1 always the
+                            descriptor-driven kernel */
   BES_T_GENERIC = 2,     /* any batched einsum; p[0] = outputs per tile,
                             p[1] = lanes per output (1,2,4,...,64),
                             p[2] = chunks of the shared contracted index

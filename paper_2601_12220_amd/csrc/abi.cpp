@@ -247,7 +247,7 @@ int bes_plan_set_config(bes_plan *plan, const bes_config *cfg) {
   }
   if (c.template_id == BES_T_FEM_STREAM) {
     if (c.p[1] < 0 || c.p[1] > 64) return fail(BES_E_INVALID, "blocks per CU must be 0..64");
-    if (c.p[2] < 0 || c.p[2] > 1) return fail(BES_E_INVALID, "FEM kernel variant must be 0 or 1");
+    if (c.p[2] < 0 || c.p[2] > 2) return fail(BES_E_INVALID, "FEM kernel variant must be 0, 1 or 2");
   }
   plan->p.cfg = c;
   return BES_OK;
@@ -319,7 +319,7 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
         p.fem_ws_device = dev;
       }
       e = bes::launch_fem(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, a, p.fem_ws, p.cfg.p[1],
-                          p.cfg.p[2] != 0, stream, (hipEvent_t)p.time_start,
+                          p.cfg.p[2], stream, (hipEvent_t)p.time_start,
                           (hipEvent_t)p.time_stop);
       if (e != hipSuccess) return hip_fail(e, "FEM-stream launch");
       return BES_OK;

@@ -313,8 +313,10 @@ bes_config default_config(const Plan &p) {
     c.p[1] = 128;
   } else if (p.fem_ok) {
     c.template_id = BES_T_FEM_STREAM;
-    c.p[0] = 64;   // elements per tile (one wave)
-    c.p[1] = 32;   // one-wave blocks per CU in the grid (measured best)
+    c.p[0] = 64;   // elements per tile
+    c.p[1] = 64;   // blocks per CU in the grid: one tile per block at
+                   // e = 2^20 (measured best for the lean kernel)
+    c.p[2] = 0;    // lean kernel, two waves per tile, where the batch allows
   } else if (template_supported(p, BES_T_GENERIC)) {
     // Lanes per output grow with the shared contraction length (about 64
     // rows per lane; the generic template splits those rows across lanes and

@@ -659,15 +659,21 @@ constexpr int kWPB = (NR * NI * NJ * (int)sizeof(T) > 12 * 1024) ? 8 : 1;
 // share u and S), one output component per member, G absent or read by every
 // member from one staged row per element (views of one buffer, such as the
 // rows of a Jacobian), dense 16-byte-aligned operands, full tiles, T[NR][NI]
-// in registers and S packed [r][j][i] within the scalar data cache.  All that
-// the tile loop addresses besides the tile index is fixed for the launch and
-// arrives in a small argument block held in scalar registers, so a tile issues
-// no scalar loads but those of S: no descriptor reads sit between one tile's
-// stores and the next tile's loads.  S is a kernel argument of its own,
-// restrict-qualified: only then may the compiler read it with scalar loads
-// across the kernel's stores (through a struct field it falls back to vector
-// loads, one per lane).  On the P3 gradient batch (e = 2^20) this
-// sustains about 1.3x the bandwidth of the descriptor-driven FAST kernel.
+// in registers and S packed [r][j][i] within the scalar data cache.
+//
+// A 64-element tile is shared by WPT waves (one block): each wave loads and
+// stores 1/WPT of the tile's rows and owns NI/WPT of the outputs i, so it
+// keeps 1/WPT of T in registers.  Two waves per tile halve each wave's
+// arithmetic phase and raise the waves resident per SIMD; while one of them
+// computes, the others' loads and stores keep HBM busy (measured on the P3
+// gradient batch: about 1.2x the bandwidth of one wave per tile).
+//
+// All that the tile loop addresses besides the tile index is fixed for the
+// launch and arrives in a small argument block held in scalar registers: no
+// descriptor reads sit between one tile's stores and the next tile's loads.
+// S is a kernel argument of its own, restrict-qualified, so the compiler may
+// read it with scalar loads across the kernel's stores (through a struct
+// field it falls back to one vector load per lane).
 // ---------------------------------------------------------------------------
 struct LeanArgs {
   const void *u;        // dense [E][NJ], offset applied
@@ -680,64 +686,117 @@ struct LeanArgs {
   int32_t g_off[3][3];  // row position of G[member][r] (unused members: 0)
 };
 
-template <typename T>
-constexpr int kLeanUnrollJ = sizeof(T) == 8 ? 2 : 4;
-
 template <typename T, int NI, int NJ, int NR>
 constexpr bool kLeanShape = kChunksOf<T, NI, NR> == 1 && kWPB<T, NI, NJ, NR> == 1;
 
+// Rows of S per scalar round trip of stage 1: 320 bytes of a wave's slice.
+template <typename T, int IH, int NJ>
+constexpr int kLeanUnrollJ = (320 / (IH * (int)sizeof(T))) < 1 ? 1
+                             : (320 / (IH * (int)sizeof(T))) > NJ ? NJ
+                                                                  : 320 / (IH * (int)sizeof(T));
+
 // No occupancy attribute here: with one, the scheduler keeps SGPR use low and
-// walks S through a single 16-SGPR window, a scalar round trip per 64 bytes
-// of S; without, it loads two rows of S per round trip (the register
-// allocation of the shapes in use still gives two waves per SIMD in FP64).
-template <typename T, int NI, int NJ, int NR, int MPG>
-__global__ void __launch_bounds__(kTile)
+// walks S through a single 16-SGPR window, one scalar round trip per 64 bytes
+// of S; without, it batches 320 bytes per round trip.
+template <typename T, int NI, int NJ, int NR, int MPG, int WPT>
+__global__ void __launch_bounds__(kTile * WPT)
     fem_lean_kernel(const LeanArgs a, const T *__restrict__ S) {
+  static_assert(kMaxRow % WPT == 0, "G row loads split evenly");
   constexpr int kR0 = NJ > NI ? NJ : NI;
-  constexpr int kRows = kR0 > kMaxRow ? kR0 : kMaxRow;
-  __shared__ T X[kRows * kPitch];
+  __shared__ T X[kR0 * kPitch];        // u rows, then one member's output rows
+  __shared__ T GX[kMaxRow * kPitch];   // the staged G rows
   using V = typename Vec16<T>::type;
+  using DU = Dense<T, NJ>;
   using DI = Dense<T, NI>;
+  constexpr int kIH = (NI + WPT - 1) / WPT;        // outputs i per wave
+  constexpr int kGK = kMaxRow / WPT;               // G-row loads per lane
+  constexpr int kUK = (DU::kVT + WPT - 1) / WPT;   // u vectors per lane
+  constexpr int kOK = (DI::kVT + WPT - 1) / WPT;   // output vectors per lane
+  // shares that divide evenly need no per-wave bounds (kept compile-time)
+  constexpr bool kUEven = DU::kVT % WPT == 0, kOEven = DI::kVT % WPT == 0;
+  constexpr bool kIEven = NI % WPT == 0;
+  const int w = WPT > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x / kTile) : 0;
   const bool has_g = a.g_w > 0;
+  const int i0 = w * kIH;                          // this wave's first output i
   for (int64_t tile = a.tile0 + blockIdx.x; tile < a.tile1; tile += gridDim.x) {
     const int lane = fresh_lane();
     const int64_t e0 = tile * kTile;
-    // raw loads of the tile: G rows (clamped, branch-free) and dense u rows
-    T rg[kMaxRow];
-    if (has_g)
-      load_block<T, kMaxRow>(rg, (const T *)a.grow + e0 * a.g_stride, false, a.g_stride, 1, a.g_w,
-                             lane);
-    T ru[Dense<T, NJ>::kLen];
-    load_dense<T, NJ>(ru, (const T *)a.u + e0 * NJ, lane);
-    // G of this lane's element for every member, through the staged row
+    // raw loads, this wave's share: G rows (clamped, branch-free), u rows
+    T rg[kGK];
+    if (has_g) {
+      const T *__restrict__ pg = (const T *)a.grow + e0 * a.g_stride;
+      const int lim = (kTile - 1) * a.g_stride + a.g_w - 1;
+#pragma unroll
+      for (int k = 0; k < kGK; ++k) {
+        const int f = lane + kTile * (k + w * kGK);
+        const int el = f / kMaxRow, c = f - el * kMaxRow;
+        const int pos = el * a.g_stride + c;
+        rg[k] = pg[pos < lim ? pos : lim];
+      }
+    }
+    T ru[kUK * DU::kV];
+    {
+      const V *__restrict__ pu = (const V *)((const T *)a.u + e0 * NJ);
+#pragma unroll
+      for (int k = 0; k < kUK; ++k) {
+        const int t = k + w * kUK;
+        int q = lane + kTile * t;
+        if (!kUEven && t >= DU::kVT) q = DU::kN - 1;   // past the last share
+        else if ((t + 1) * kTile > DU::kN) q = q < DU::kN ? q : DU::kN - 1;
+        const V x = __builtin_nontemporal_load(&pu[q]);   // streamed once
+#pragma unroll
+        for (int sv = 0; sv < DU::kV; ++sv) ru[k * DU::kV + sv] = x[sv];
+      }
+    }
+    // transposes into [component][element]
+    if (has_g) {
+#pragma unroll
+      for (int k = 0; k < kGK; ++k) {
+        const int f = lane + kTile * (k + w * kGK);
+        const int el = f / kMaxRow, c = f - el * kMaxRow;
+        GX[c * kPitch + el] = rg[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kUK; ++k) {
+      const int t = k + w * kUK;
+#pragma unroll
+      for (int sv = 0; sv < DU::kV; ++sv) {
+        const int f = DU::kV * (lane + kTile * t) + sv;
+        const int el = f / NJ, c = f - el * NJ;
+        if ((kUEven || t < DU::kVT) && ((t + 1) * kTile <= DU::kN || f < NJ * kTile))
+          X[c * kPitch + el] = ru[k * DU::kV + sv];
+      }
+    }
+    __syncthreads();
+    // G of this lane's element for every member
     T gm[MPG][NR];
     if (has_g) {
-      put_block<T, kMaxRow>(X, rg, lane);
-      __syncthreads();
 #pragma unroll
       for (int q = 0; q < MPG; ++q)
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gm[q][r] = X[a.g_off[q][r] * kPitch + lane];
-      __syncthreads();
+        for (int r = 0; r < NR; ++r) gm[q][r] = GX[a.g_off[q][r] * kPitch + lane];
     }
-    put_dense<T, NJ>(X, ru, lane);
-    __syncthreads();
-    // stage 1: T[r][i] = sum_j S[r][j][i] u[j], S wave-uniform
-    T t[NR][NI];
+    // stage 1, this wave's outputs: T[r][ii] = sum_j S[r][j][i0 + ii] u[j]
+    T t[NR][kIH];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-      for (int i = 0; i < NI; ++i) t[r][i] = 0;
+      for (int ii = 0; ii < kIH; ++ii) t[r][ii] = 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int xl = fresh_lane();   // u re-read per r instead of pinned in VGPRs
-      // 320 bytes of S per scalar round trip: two rows in FP64, four in FP32
-#pragma unroll(kLeanUnrollJ<T>)
+#pragma unroll(kLeanUnrollJ<T, kIH, NJ>)
       for (int j = 0; j < NJ; ++j) {
         const T uj = X[j * kPitch + xl];
         const T *__restrict__ Srow = S + (r * NJ + j) * NI;
 #pragma unroll
-        for (int i = 0; i < NI; ++i) t[r][i] = fma(Srow[i], uj, t[r][i]);
+        for (int ii = 0; ii < kIH; ++ii) {
+          // NI not a multiple of WPT: the last wave's extra output re-reads
+          // the row's last value (never stored)
+          const int i = kIEven ? i0 + ii : (i0 + ii < NI ? i0 + ii : NI - 1);
+          t[r][ii] = fma(Srow[i], uj, t[r][ii]);
+        }
       }
     }
     __syncthreads();
@@ -746,20 +805,21 @@ __global__ void __launch_bounds__(kTile)
     for (int q = 0; q < MPG; ++q) {
       if (q >= a.n_mem) break;
 #pragma unroll
-      for (int i = 0; i < NI; ++i) {
-        T acc = t[0][i];
+      for (int ii = 0; ii < kIH; ++ii) {
+        T acc = t[0][ii];
         if (has_g) {
-          acc = gm[q][0] * t[0][i];
+          acc = gm[q][0] * t[0][ii];
 #pragma unroll
-          for (int r = 1; r < NR; ++r) acc = fma(gm[q][r], t[r][i], acc);
+          for (int r = 1; r < NR; ++r) acc = fma(gm[q][r], t[r][ii], acc);
         }
-        X[i * kPitch + lane] = acc;
+        if (kIEven || i0 + ii < NI) X[(i0 + ii) * kPitch + lane] = acc;
       }
       __syncthreads();
       V *__restrict__ ov = (V *)((T *)a.out[q] + e0 * NI);
 #pragma unroll
-      for (int k = 0; k < DI::kVT; ++k) {
-        const int v = lane + kTile * k;
+      for (int k = 0; k < kOK; ++k) {
+        const int tt = k + w * kOK;
+        const int v = lane + kTile * tt;
         V vv;
 #pragma unroll
         for (int sv = 0; sv < DI::kV; ++sv) {
@@ -767,7 +827,8 @@ __global__ void __launch_bounds__(kTile)
           const int el = f / NI, ic = f - el * NI;
           vv[sv] = X[ic * kPitch + (el < kTile ? el : 0)];
         }
-        if ((k + 1) * kTile <= DI::kN || v < DI::kN) __builtin_nontemporal_store(vv, &ov[v]);
+        if ((kOEven || tt < DI::kVT) && ((tt + 1) * kTile <= DI::kN || v < DI::kN))
+          __builtin_nontemporal_store(vv, &ov[v]);
       }
       __syncthreads();
     }
@@ -775,12 +836,20 @@ __global__ void __launch_bounds__(kTile)
 }
 
 template <typename T, int NI, int NJ, int NR>
-hipError_t launch_lean(const LeanArgs &a, const T *spack, int mpg, dim3 grid, hipStream_t s) {
+hipError_t launch_lean(const LeanArgs &a, const T *spack, int mpg, int wpt, dim3 grid,
+                       hipStream_t s) {
   if constexpr (kLeanShape<T, NI, NJ, NR>) {
-    if (mpg == 1)
-      hipLaunchKernelGGL((fem_lean_kernel<T, NI, NJ, NR, 1>), grid, dim3(kTile), 0, s, a, spack);
-    else
-      hipLaunchKernelGGL((fem_lean_kernel<T, NI, NJ, NR, 3>), grid, dim3(kTile), 0, s, a, spack);
+#define BES_LEAN_LAUNCH(MPG, WPT)                                                         \
+  hipLaunchKernelGGL((fem_lean_kernel<T, NI, NJ, NR, MPG, WPT>), grid, dim3(kTile * WPT), 0, s, \
+                     a, spack)
+    if (mpg == 1) {
+      if (wpt == 2) BES_LEAN_LAUNCH(1, 2);
+      else BES_LEAN_LAUNCH(1, 1);
+    } else {
+      if (wpt == 2) BES_LEAN_LAUNCH(3, 2);
+      else BES_LEAN_LAUNCH(3, 1);
+    }
+#undef BES_LEAN_LAUNCH
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1080,7 +1149,7 @@ size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR) {
 }
 
 hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
-                      int blocks_per_cu, bool descriptor_kernel, hipStream_t stream, hipEvent_t ev_start,
+                      int blocks_per_cu, int variant, hipStream_t stream, hipEvent_t ev_start,
                       hipEvent_t ev_stop) {
   if (a.E <= 0) return hipSuccess;
   if (!workspace) return hipErrorInvalidValue;
@@ -1196,7 +1265,7 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
                c.grp[g].ss[1] == c.grp[0].ss[1] && c.grp[g].ss[2] == c.grp[0].ss[2];
   // Lean variant: one group, one output component per member, G absent or
   // one shared row of plain views.
-  bool use_lean = !descriptor_kernel && !use_mfma && fast_ok && full_tiles > 0 && NX == 1 && !ew &&
+  bool use_lean = variant != 1 && !use_mfma && fast_ok && full_tiles > 0 && NX == 1 && !ew &&
                   c.n_groups == 1 &&
                   pk.transposed && c.n_members <= 3 && c.grp[0].m0 == 0 &&
                   c.grp[0].m1 == c.n_members && lean_shape(f64, NI, NJ, NR);
@@ -1234,13 +1303,15 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
   }
   if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
   if (use_lean) {
+    const int wpt = variant == 2 ? 1 : 2;       // waves per tile
     dim3 lgrid((unsigned)std::min<int64_t>(full_tiles, cap));
     e = hipErrorInvalidValue;
 #define BES_FEM_LEAN_DISPATCH(ni, nj, nr, nx)                                                  \
     if (NI == ni && NJ == nj && NR == nr && nx == 1)                                          \
-      e = f64 ? launch_lean<double, ni, nj, nr>(la, (const double *)workspace, mpg, lgrid,    \
-                                                stream)                                      \
-              : launch_lean<float, ni, nj, nr>(la, (const float *)workspace, mpg, lgrid, stream);
+      e = f64 ? launch_lean<double, ni, nj, nr>(la, (const double *)workspace, mpg, wpt, lgrid, \
+                                                stream)                                        \
+              : launch_lean<float, ni, nj, nr>(la, (const float *)workspace, mpg, wpt, lgrid,  \
+                                               stream);
     BES_FEM_SHAPES(BES_FEM_LEAN_DISPATCH)
 #undef BES_FEM_LEAN_DISPATCH
     if (e != hipSuccess) return e;

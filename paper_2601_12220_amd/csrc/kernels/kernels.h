@@ -13,14 +13,15 @@ int device_cu_count();
 
 // FEM-stream template: a pack of S into `workspace` (at least
 // fem_workspace_bytes) followed by the stream kernel with `blocks_per_cu`
-// one-wave blocks per compute unit walking 64-element tiles.  Plain batches
-// (one stage-1 group, one output component per member) run the lean kernel
-// unless `descriptor_kernel` asks for the descriptor-driven one.
+// blocks per compute unit walking 64-element tiles.  `variant`: 0 runs plain
+// batches (one stage-1 group, one output component per member) on the lean
+// kernel with two waves per tile, 2 on the lean kernel with one wave per
+// tile, 1 always on the descriptor-driven kernel.
 size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR);
 // `ev_start` / `ev_stop` (may be NULL) are recorded on `stream` right before
 // and after the stream kernel(s), after the re-layout of S.
 hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
-                      int blocks_per_cu, bool descriptor_kernel, hipStream_t stream,
+                      int blocks_per_cu, int variant, hipStream_t stream,
                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Generic template: one launch over (slot, tile) pairs.  `dev` is the device

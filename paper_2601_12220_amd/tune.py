@@ -27,13 +27,14 @@ T_MFMA = 3
 def candidates(template_id: int) -> List[Tuple[int, ...]]:
     """Parameter tuples (template id first) the tuner tries for a template.
 
-    FEM stream: p[1] = one-wave blocks per compute unit in the grid, p[2] = 1
-                for the descriptor-driven kernel instead of the lean one.
+    FEM stream: p[1] = blocks per compute unit in the grid, p[2] = kernel
+                variant (0 lean with two waves per tile, 2 lean with one,
+                1 descriptor-driven).
     Generic:    p[0] = outputs per tile, p[1] = lanes per output, p[2] = chunks
                 of the shared contracted space (their sums add into the output).
     MFMA:       the single 128 x 128 tile shape the template implements."""
     if template_id == T_FEM_STREAM:
-        return [(T_FEM_STREAM, 64, b, v) for v in (0, 1) for b in (8, 16, 32, 64)]
+        return [(T_FEM_STREAM, 64, b, v) for v in (0, 2, 1) for b in (8, 16, 32, 64)]
     if template_id == T_GENERIC:
         # p[2]: chunks of the shared contracted space per output (1: none)
         return ([(T_GENERIC, tile, lanes, 1) for tile in (64, 256, 1024) for lanes in (1, 4, 16, 64)]
@@ -68,7 +69,7 @@ def time_launches(launch, stream, reps: int, warmup: int) -> float:
 
 
 def tune(ctx, plan, buffers: Dict[str, object], outputs: Sequence[object], stream=None,
-         reps: int = 10, warmup: int = 2, arch: str = "gfx950",
+         reps: int = 20, warmup: int = 3, arch: str = "gfx950",
          record: bool = True) -> Optional[TuneResult]:
     """Time every candidate of the plan's current template on ``buffers`` /
     ``outputs`` (device tensors), install the fastest in the plan and, with

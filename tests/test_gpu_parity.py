@@ -86,12 +86,12 @@ def test_config2_full_size(ctx, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("bpc", [1, 64])
 def test_config2_kernel_variants(ctx, dtype, variant, bpc):
-    """The lean kernel (variant 0) and the descriptor-driven one (1) on the
-    P3 gradient batch with a ragged tail; one block per CU makes every block
-    walk several tiles."""
+    """The lean kernel with two waves per tile (variant 0) and one (2), and
+    the descriptor-driven one (1), on the P3 gradient batch with a ragged
+    tail; one block per CU makes every block walk several tiles."""
     w = workloads.config2(e=64 * 1093 + 29, dtype=dtype)
     p = ctx.register(w.notation, w.table, w.operands)
     p.set_config(capi.BES_T_FEM_STREAM, 64, bpc, variant)
@@ -115,7 +115,7 @@ def test_lean_kernel_one_member_and_without_g(ctx, dtype):
     for w in (one, no_g):
         p = ctx.register(w.notation, w.table, w.operands)
         assert p.template == "fem_stream"
-        for variant in (0, 1):
+        for variant in (0, 1, 2):
             p.set_config(capi.BES_T_FEM_STREAM, 64, 16, variant)
             _check_full(p, w)
 

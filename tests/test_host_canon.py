@@ -452,13 +452,13 @@ def test_adjoint_of_dense_pair(ctx):
 
 def test_fem_config_validation(ctx):
     """FEM-stream parameters outside their documented ranges are rejected:
-    blocks per compute unit 0..64, kernel variant 0 (lean where the batch
-    allows) or 1 (descriptor-driven)."""
+    blocks per compute unit 0..64, kernel variant 0 (lean, two waves per
+    tile), 1 (descriptor-driven) or 2 (lean, one wave per tile)."""
     w = workloads.config2(e=1000)
     p = ctx.register(w.notation, w.table, w.operands)
-    for good in ((64, 1, 0), (64, 64, 1)):
+    for good in ((64, 1, 0), (64, 64, 1), (64, 8, 2)):
         p.set_config(capi.BES_T_FEM_STREAM, *good)
-    for bad in ((64, 65, 0), (64, -1, 0), (64, 16, 2), (64, 16, -1)):
+    for bad in ((64, 65, 0), (64, -1, 0), (64, 16, 3), (64, 16, -1)):
         with pytest.raises(capi.BesError):
             p.set_config(capi.BES_T_FEM_STREAM, *bad)
 
