@@ -47,6 +47,44 @@ constexpr int kTile = 64;      // elements per wave tile = lanes per wave
 constexpr int kPitch = kTile + 1;
 constexpr int kMaxRow = 12;    // staged G row width (TET: 4 x 3 vertex coords)
 
+// FP64 sin (shift 0) or cos (shift 1) for |x| < 2^20: Cody-Waite reduction
+// r = x - n pi/2 with pi/2 split in three parts (the first two with 33
+// significant bits, so n times them is exact for |n| < 2^20), then the Taylor
+// series of sin and cos on [-pi/4, pi/4] to degrees 19 and 20 (truncation
+// below 1e-19), chosen and signed by the quadrant n mod 4: about 30 FP64
+// operations.  Callers check the range for the whole wave first.
+__device__ __forceinline__ double sincos_small(double x, int shift) {
+  const double n = rint(x * 0x1.45f306dc9c883p-1);   // x * 2/pi
+  double r = fma(-n, 0x1.921fb54400000p+0, x);
+  r = fma(-n, 0x1.0b4611a600000p-34, r);
+  r = fma(-n, 0x1.3198a2e037073p-69, r);
+  const double r2 = r * r;
+  double ps = -1.0 / 121645100408832000.0;           // -1/19!
+  ps = fma(ps, r2, 1.0 / 355687428096000.0);          //  1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);           // -1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);               //  1/13!
+  ps = fma(ps, r2, -1.0 / 39916800.0);                // -1/11!
+  ps = fma(ps, r2, 1.0 / 362880.0);                   //  1/9!
+  ps = fma(ps, r2, -1.0 / 5040.0);                    // -1/7!
+  ps = fma(ps, r2, 1.0 / 120.0);                      //  1/5!
+  ps = fma(ps, r2, -1.0 / 6.0);                       // -1/3!
+  const double sr = fma(ps * r2, r, r);
+  double pc = 1.0 / 2432902008176640000.0;            //  1/20!
+  pc = fma(pc, r2, -1.0 / 6402373705728000.0);        // -1/18!
+  pc = fma(pc, r2, 1.0 / 20922789888000.0);           //  1/16!
+  pc = fma(pc, r2, -1.0 / 87178291200.0);             // -1/14!
+  pc = fma(pc, r2, 1.0 / 479001600.0);                //  1/12!
+  pc = fma(pc, r2, -1.0 / 3628800.0);                 // -1/10!
+  pc = fma(pc, r2, 1.0 / 40320.0);                    //  1/8!
+  pc = fma(pc, r2, -1.0 / 720.0);                     // -1/6!
+  pc = fma(pc, r2, 1.0 / 24.0);                       //  1/4!
+  pc = fma(pc, r2, -0.5);                             // -1/2!
+  const double cr = fma(pc, r2, 1.0);
+  const int q = ((int)n + shift) & 3;
+  const double v = (q & 1) ? cr : sr;
+  return (q & 2) ? -v : v;
+}
+
 template <typename T>
 __device__ __forceinline__ T apply_op(int op, T v) {
   switch (op) {
@@ -1006,8 +1044,20 @@ __global__ void __launch_bounds__(kTile * kMW) __attribute__((amdgpu_waves_per_e
         if (G.u.kind == FEM_SRC_ELEMENTWISE) {
           const double alpha = G.u.alpha, beta = G.u.beta;
           const int op = G.u.op;
+          // sin / cos: the short reduction when every value of the wave is
+          // below 2^20 in magnitude (a wave-uniform branch), else the library
+          bool small = true;
 #pragma unroll
-          for (int k = 0; k < D::kLen; ++k) ru[k] = alpha * apply_op<double>(op, ru[k]) + beta + rw[k];
+          for (int k = 0; k < D::kLen; ++k) small = small && fabs(ru[k]) < 0x1p20;
+          const bool trig = op == BES_OP_SIN || op == BES_OP_COS;
+          if (trig && __builtin_amdgcn_ballot_w64(!small) == 0) {
+            const int shift = op == BES_OP_COS ? 1 : 0;
+#pragma unroll
+            for (int k = 0; k < D::kLen; ++k) ru[k] = alpha * sincos_small(ru[k], shift) + beta + rw[k];
+          } else {
+#pragma unroll
+            for (int k = 0; k < D::kLen; ++k) ru[k] = alpha * apply_op<double>(op, ru[k]) + beta + rw[k];
+          }
         }
       }
       double af[4][M::kKB];

@@ -128,6 +128,27 @@ def test_config3_small(ctx, e):
     _check_full(p, w)
 
 
+@pytest.mark.parametrize("op", ["sin", "cos"])
+def test_functional_trig_ranges(ctx, op):
+    """The P4 prologue's two trigonometric paths: the short reduction for
+    waves whose arguments all stay below 2^20 in magnitude and the library
+    routine for a wave holding a larger one (tile 3 gets |a| up to 1e9),
+    for sin and cos, against the oracle."""
+    import dataclasses
+    w = workloads.config3(e=64 * 8 + 5)
+    a0 = w.buffers["a0"].clone()
+    a0[3 * 64 + 7, 11] = 1.0e9
+    a0[3 * 64 + 40, :] *= 3.0e6
+    a0[5 * 64:6 * 64, :] *= 40.0                     # |a| in the hundreds
+    bufs = dict(w.buffers, a0=a0)
+    ops = {k: (dataclasses.replace(v, op=op) if v.kind == "elementwise" else v)
+           for k, v in w.operands.items()}
+    w2 = workloads.Workload(w.name + "_" + op, w.notation, w.table, ops, bufs, w.dtype, w.info)
+    p = ctx.register(w2.notation, w2.table, w2.operands)
+    assert p.template == "fem_stream"
+    _check_full(p, w2)
+
+
 def test_config3_full_size(ctx):
     w = workloads.config3()
     p = ctx.register(w.notation, w.table, w.operands)
