@@ -179,3 +179,62 @@ def test_grad_at_matches_full_grad(notation, shapes):
         pos = np.arange(full.size)
         np.testing.assert_allclose(oracle.einsum_grad_at(notation, ops, G, k, pos),
                                    full.ravel(), rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Element-wise functional operands with a second source (Definition
+# "Functional Batched Einstein Summation": an argument is replaced by a
+# function of its index tuple; here alpha * op(S0[idx]) + beta + S1[idx]).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("op,args,values", [
+    # arguments at which the function value is fixed by the mathematics and
+    # exactly representable (sin pi/2 = 1 and cos pi = -1 round exactly in
+    # FP64; the squares are exact binary fractions)
+    ("sin", [0.0, np.pi / 2, -np.pi / 2, np.pi / 6], [0.0, 1.0, -1.0, 0.5]),
+    ("cos", [0.0, np.pi, 2 * np.pi, np.pi / 3], [1.0, -1.0, 1.0, 0.5]),
+    ("square", [0.0, 3.0, -0.5, 1.5], [0.0, 9.0, 0.25, 2.25]),
+    ("id", [0.0, 3.0, -0.5, 1.5], [0.0, 3.0, -0.5, 1.5]),
+])
+@pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (2.0, 0.5), (-3.0, 1.25)])
+def test_elementwise_two_sources_known_values(op, args, values, alpha, beta):
+    # b is chosen so that every plausible mis-wiring gives another value:
+    # dropping b, adding it inside alpha*op(.) (alpha != 1), applying op to
+    # it, or swapping the two sources.
+    a = np.array(args)
+    b = np.array([0.25, -1.5, 2.0, 0.75])
+    got = F.elementwise(a, op, alpha, beta, b)
+    want = alpha * np.array(values) + beta + b
+    # pi/6 and pi/3 are rounded arguments: the values hold within a few ulp
+    np.testing.assert_allclose(got, want, rtol=0, atol=4e-15)
+    # the single-source form is the same without b
+    np.testing.assert_allclose(F.elementwise(a, op, alpha, beta), want - b, rtol=0, atol=4e-15)
+
+
+def test_elementwise_second_source_is_added_outside_alpha():
+    # alpha * op(a) + beta + b with a = 0 under sin: the value is beta + b
+    # whatever alpha is; alpha * (op(a) + b) + beta would give beta + alpha b.
+    a = np.zeros(3)
+    b = np.array([1.0, -2.0, 4.0])
+    for alpha in (2.0, -1.0, 10.0):
+        np.testing.assert_array_equal(F.elementwise(a, "sin", alpha, 0.5, b), 0.5 + b)
+
+
+def test_functional_p4_batch_against_hand_materialized_numpy():
+    # A tiny instance of the functional P4 batch 'rij,exr,ej->exi' built by
+    # the seeded workload generator, evaluated along the oracle's own path
+    # (operand materialization, then the loop nest), against numpy.einsum on
+    # operands materialized by hand from their definitions:
+    #   u_k[e, j] = sin(a_k[e, j]) + b_k[e, j]
+    #   J[e, x, r] = V[e, r + 1, x] - V[e, 0, x]   (affine tetrahedron map)
+    import workloads
+    from tests.gpu_util import oracle_full
+    w = workloads.config3(e=9, ni=5)
+    got = oracle_full(w)
+    V = w.buffers["V"].numpy()
+    J = np.transpose(V[:, 1:, :] - V[:, :1, :], (0, 2, 1))
+    D = w.buffers["D"].numpy()
+    for k in range(4):
+        u = np.sin(w.buffers[f"a{k}"].numpy()) + w.buffers[f"b{k}"].numpy()
+        ref = np.einsum("rij,exr,ej->exi", D, J, u)
+        np.testing.assert_allclose(got[k], ref, rtol=1e-13, atol=1e-13)
