@@ -270,7 +270,7 @@ def _run_dense_on(be, bufs, stream, steps, warmup, fwd_flops):
         torch.autograd.backward(outs, G)
         for t in leaves.values():
             t.grad = None
-    ms_fb = time_launches(fwd_bwd, max(2, steps // 2), 1, stream)
+    ms_fb = time_launches(fwd_bwd, max(20, steps // 2), 2, stream)
     ms_b = max(ms_fb - ms_f, 1e-6)
     res = {"template": be.plan.template, "ms_forward": round(ms_f, 4),
            "TFLOP/s_forward": round(fwd_flops / (ms_f * 1e-3) / 1e12, 1),

@@ -217,6 +217,28 @@ int bes_ctx_stats(const bes_ctx *ctx, int64_t *hits, int64_t *misses);
 int bes_launch(const bes_plan *plan, const void *const *src_ptrs,
                void *const *out_ptrs, void *hip_stream);
 
+/* Output layout of output slot `slot` (0 .. number of outputs - 1: the b
+ * members of a plain plan in user order, the n_out outputs of an adjoint
+ * plan).  The launch writes element (i_1, ..., i_k) of that output, indices
+ * in the notation's output order, at out_ptrs[slot] + offset + sum_d i_d *
+ * strides[d] (elements), and with accumulate != 0 adds its value to what is
+ * there instead of overwriting it.  strides == NULL and offset == 0 restore
+ * dense row-major.  This is how an adjoint writes the gradient of a VIEW
+ * argument straight into its source buffer's gradient and how gradients of
+ * one buffer from several operand positions are summed (Section "Batched
+ * Einstein Summation": a shared argument's gradient is the sum over every
+ * slot that reads it).  Accumulating outputs that overlap in memory are
+ * added atomically; overwritten outputs must not overlap.  The FEM-stream
+ * template overwrites only: a plan that accumulates is evaluated by the
+ * generic template.  The caller owns the memory; makes no HIP call. */
+int bes_plan_set_output(bes_plan *plan, int32_t slot, int64_t offset, const int64_t *strides,
+                        int32_t accumulate);
+
+/* Zero n elements of `dtype` (BES_FLOAT32 / BES_FLOAT64) at device pointer
+ * ptr on `hip_stream` with a fill kernel (no memset node, so it can be
+ * captured in a HIP graph).  For gradients that only accumulate. */
+int bes_fill_zero(void *ptr, int64_t n, int32_t dtype, void *hip_stream);
+
 /* Profiling hook.  With both events non-NULL (hipEvent_t handles the caller
  * owns and keeps alive), every later bes_launch of the plan records
  * start_event on its stream right before the plan's evaluation kernel(s) and
@@ -248,9 +270,14 @@ void bes_batch_destroy(bes_batch *batch);
  *   shape), then the forward plan's src_ptrs] and out_ptrs = one pointer per
  *   distinct position-`pos` argument, in order of first occurrence down the
  *   rows (n_out receives that count).  Outputs are dense in the argument's
- *   shape; for a VIEW argument the gradient of the view is written dense.
- * BES_E_UNSUPPORTED if the position has a repeated index or a functional
- * argument that is not an ARRAY/VIEW. */
+ *   shape and overwritten by default; bes_plan_set_output on the adjoint plan
+ *   writes the gradient of a VIEW argument through the view's offset and
+ *   strides into its source's gradient, and accumulates into a gradient that
+ *   another position or plan already wrote.
+ * BES_E_UNSUPPORTED if the position has a repeated index.  Functional
+ * arguments at other positions are evaluated as in the forward plan; the
+ * gradient with respect to the sources of a functional (ELEMENTWISE,
+ * TET_JACOBIAN) argument is not provided. */
 int bes_adjoint(bes_ctx *ctx, const bes_plan *fwd, int32_t pos,
                 bes_plan **out, int32_t *n_out);
 

@@ -108,6 +108,8 @@ def load():
         "bes_batch_launch": ([P, ctypes.POINTER(PP), ctypes.POINTER(PP), P], i32),
         "bes_batch_destroy": ([P], None),
         "bes_adjoint": ([P, P, i32, PP, i32p], i32),
+        "bes_plan_set_output": ([P, i32, ctypes.c_int64, i64p, i32], i32),
+        "bes_fill_zero": ([P, ctypes.c_int64, i32, P], i32),
         "bes_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -287,3 +289,16 @@ def bes_adjoint(ctx, fwd, pos: int):
     rc = load().bes_adjoint(ctx, fwd, pos, ctypes.byref(h), ctypes.byref(n))
     check(rc, "bes_adjoint")
     return h, n.value, rc
+
+
+def bes_plan_set_output(h, slot: int, offset: int = 0, strides=None, accumulate: bool = False):
+    st = None
+    if strides is not None:
+        st = (ctypes.c_int64 * max(1, len(strides)))(*[int(v) for v in strides])
+    check(load().bes_plan_set_output(h, slot, int(offset), st, 1 if accumulate else 0),
+          "bes_plan_set_output")
+
+
+def bes_fill_zero(ptr: int, n: int, dtype: int, stream: int = 0) -> None:
+    check(load().bes_fill_zero(ctypes.c_void_p(ptr), int(n), dtype, ctypes.c_void_p(stream)),
+          "bes_fill_zero")

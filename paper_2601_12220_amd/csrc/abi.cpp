@@ -88,39 +88,87 @@ bool env_flag(const char *name) {
   return s && *s && std::strcmp(s, "0") != 0;
 }
 
-// Device copy of the plan's generic descriptor for config `cfg`; re-uploaded
-// only when the config or the device changes (after draining the device, so
-// no launch in flight still reads the old copy).
-hipError_t ensure_generic_dev(const bes::Plan &p, const GenEinsum &g, const bes_config &cfg) {
+// The plan's generic descriptor for `cfg` and its current output layouts on
+// the current device: bound once into pinned host memory and uploaded with an
+// asynchronous copy on `stream` (ordered before the kernel that reads it).
+// Entries live until the plan is destroyed.
+int generic_descriptor(const bes::Plan &p, const bes_config &cfg, hipStream_t stream,
+                       const bes::Plan::GenCopy **out, std::string &err) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  bool same_cfg = std::memcmp(&p.gen_dev_cfg, &cfg, sizeof cfg) == 0;
-  if (p.gen_dev && p.gen_dev_device == dev && same_cfg) return hipSuccess;
-  if (p.gen_dev) {
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+  if (e != hipSuccess) {
+    err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return BES_E_HIP;
   }
-  if (p.gen_dev && p.gen_dev_device != dev) {
-    (void)hipFree(p.gen_dev);
-    p.gen_dev = nullptr;
-  }
-  if (!p.gen_dev) {
-    e = hipMalloc(&p.gen_dev, sizeof(GenEinsum));
-    if (e != hipSuccess) {
-      p.gen_dev = nullptr;
-      return e;
+  for (const auto &c : p.gen_cache)
+    if (c.device == dev && bes::same_layouts(c.layouts, p.out_layout) &&
+        std::memcmp(&c.cfg, &cfg, sizeof cfg) == 0) {
+      *out = &c;
+      return BES_OK;
     }
+  bes::Plan::GenCopy c;
+  c.cfg = cfg;
+  c.layouts = p.out_layout;
+  c.device = dev;
+  if ((e = hipHostMalloc((void **)&c.host, sizeof(GenEinsum))) != hipSuccess) {
+    err = std::string("pinned descriptor: ") + hipGetErrorString(e);
+    return BES_E_NOMEM;
   }
-  e = hipMemcpy(p.gen_dev, &g, sizeof g, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return e;
-  p.gen_dev_device = dev;
-  p.gen_dev_cfg = cfg;
-  return hipSuccess;
+  int rc = bes::bind_generic_static(p, cfg, *c.host, err);
+  if (rc) {
+    (void)hipHostFree(c.host);
+    return rc;
+  }
+  if ((e = hipMalloc((void **)&c.dev, sizeof(GenEinsum))) != hipSuccess ||
+      (e = hipMemcpyAsync(c.dev, c.host, sizeof(GenEinsum), hipMemcpyHostToDevice, stream)) !=
+          hipSuccess) {
+    if (c.dev) (void)hipFree(c.dev);
+    (void)hipHostFree(c.host);
+    err = std::string("generic descriptor upload: ") + hipGetErrorString(e);
+    return BES_E_HIP;
+  }
+  p.gen_cache.push_back(c);
+  *out = &p.gen_cache.back();
+  return BES_OK;
+}
+
+void free_gen_cache(const bes::Plan &p) {
+  for (auto &c : p.gen_cache) {
+    if (c.dev) (void)hipFree(c.dev);
+    if (c.host) (void)hipHostFree(c.host);
+  }
+  p.gen_cache.clear();
+}
+
+// Byte range [lo, hi) that output slot s of a launch touches.
+void slot_range(const bes::Plan &p, int s, const void *base, uintptr_t &lo, uintptr_t &hi) {
+  const int64_t item = p.spec.dtype == BES_FLOAT64 ? 8 : 4;
+  const std::vector<int64_t> st = bes::out_strides(p, s);
+  int64_t a = p.out_layout[s].custom ? p.out_layout[s].offset : 0, b = a;
+  for (size_t d = 0; d < p.spec.out.size(); ++d) {
+    const int64_t span = (p.spec.extent[p.spec.out[d]] - 1) * st[d];
+    if (span < 0) a += span;
+    else b += span;
+  }
+  lo = (uintptr_t)base + a * item;
+  hi = (uintptr_t)base + (b + 1) * item;
+}
+
+// Do two accumulating slots of this launch address overlapping memory?
+bool accumulating_slots_overlap(const bes::Plan &p, void *const *out) {
+  if (!bes::any_accumulate(p) || p.n_slots < 2) return false;
+  std::vector<uintptr_t> lo(p.n_slots), hi(p.n_slots);
+  for (int s = 0; s < p.n_slots; ++s) slot_range(p, s, out[s], lo[s], hi[s]);
+  for (int s = 0; s < p.n_slots; ++s)
+    for (int t = s + 1; t < p.n_slots; ++t)
+      if (lo[s] < hi[t] && lo[t] < hi[s]) return true;
+  return false;
 }
 
 int hip_fail(hipError_t e, const char *what) {
   return fail(BES_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
+
 
 }  // namespace
 
@@ -168,7 +216,7 @@ int bes_register(bes_ctx *ctx, const char *notation, int32_t b, int32_t n, int32
 
 void bes_plan_destroy(bes_plan *plan) {
   if (!plan) return;
-  if (plan->p.gen_dev) (void)hipFree(plan->p.gen_dev);
+  free_gen_cache(plan->p);
   if (plan->p.fem_ws) (void)hipFree(plan->p.fem_ws);
   delete plan;
 }
@@ -299,8 +347,32 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
   const bool f64 = p.spec.dtype == BES_FLOAT64;
   std::string err;
   hipError_t e;
+  auto record = [&](void *ev) -> hipError_t {
+    return ev ? hipEventRecord((hipEvent_t)ev, stream) : hipSuccess;
+  };
+  // The generic template evaluates every plan within its limits and honours
+  // every output layout; the others hand over to it where they cannot.
+  auto run_generic = [&](bes_config gc) -> int {
+    if (gc.template_id != BES_T_GENERIC) {
+      gc = bes_config{};
+      gc.template_id = BES_T_GENERIC;
+      gc.p[0] = 256;
+      gc.p[1] = 1;
+    }
+    const bes::Plan::GenCopy *gd = nullptr;
+    int rc = generic_descriptor(p, gc, stream, &gd, err);
+    if (rc) return fail(rc, err);
+    GenPtrs ptrs;
+    bes::bind_generic_ptrs(p, src.data(), out_ptrs, ptrs);
+    if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
+    e = bes::launch_generic(f64, gd->dev, *gd->host, ptrs, stream);
+    if (e != hipSuccess) return hip_fail(e, "generic launch");
+    if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
+    return BES_OK;
+  };
   switch (p.cfg.template_id) {
     case BES_T_FEM_STREAM: {
+      if (bes::any_accumulate(p)) return run_generic(p.cfg);
       FemArgs a;
       int rc = bes::bind_fem(p, src.data(), out_ptrs, a, err);
       if (rc) return fail(rc, err);
@@ -325,58 +397,52 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
       return BES_OK;
     }
     case BES_T_MFMA: {
+      // accumulating slots that overlap in memory need the atomic adds of
+      // the generic template
+      if (accumulating_slots_overlap(p, out_ptrs)) return run_generic(p.cfg);
       MfmaArgs a;
       int rc = bes::bind_mfma(p, src.data(), out_ptrs, a, err);
+      if (rc == BES_E_UNSUPPORTED) return run_generic(p.cfg);  // output layout
       if (rc) return fail(rc, err);
-      if (p.time_start && (e = hipEventRecord((hipEvent_t)p.time_start, stream)) != hipSuccess)
-        return hip_fail(e, "timing event");
+      if (!bes::mfma_args_ok(a)) return run_generic(p.cfg);  // unaligned rows
+      if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
       e = bes::launch_mfma(a, p.cfg.p[0], p.cfg.p[1], stream);
-      if (e == hipSuccess && p.time_stop &&
-          (e = hipEventRecord((hipEvent_t)p.time_stop, stream)) != hipSuccess)
-        return hip_fail(e, "timing event");
-      if (e == hipSuccess) return BES_OK;
-      if (e != hipErrorInvalidValue) return hip_fail(e, "MFMA launch");
-      // unaligned rows for the vector tile loads: evaluate with the generic
-      // template instead
-      [[fallthrough]];
-    }
-    case BES_T_GENERIC: {
-      bes_config gc = p.cfg;
-      if (gc.template_id != BES_T_GENERIC) {  // fallback from another template
-        gc = bes_config{};
-        gc.template_id = BES_T_GENERIC;
-        gc.p[0] = 256;
-        gc.p[1] = 1;
-      }
-      GenEinsum *g = new (std::nothrow) GenEinsum;
-      if (!g) return fail(BES_E_NOMEM, "out of host memory");
-      int rc = bes::bind_generic_static(p, gc, *g, err);
-      if (rc) {
-        delete g;
-        return fail(rc, err);
-      }
-      e = ensure_generic_dev(p, *g, gc);
-      if (e != hipSuccess) {
-        delete g;
-        return hip_fail(e, "generic descriptor upload");
-      }
-      GenPtrs ptrs;
-      bes::bind_generic_ptrs(p, src.data(), out_ptrs, ptrs);
-      if (p.time_start && (e = hipEventRecord((hipEvent_t)p.time_start, stream)) != hipSuccess) {
-        delete g;
-        return hip_fail(e, "timing event");
-      }
-      e = bes::launch_generic(f64, (const GenEinsum *)p.gen_dev, *g, ptrs, stream);
-      delete g;
-      if (e != hipSuccess) return hip_fail(e, "generic launch");
-      if (p.time_stop && (e = hipEventRecord((hipEvent_t)p.time_stop, stream)) != hipSuccess)
-        return hip_fail(e, "timing event");
+      if (e != hipSuccess) return hip_fail(e, "MFMA launch");
+      if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
       return BES_OK;
     }
+    case BES_T_GENERIC:
+      return run_generic(p.cfg);
     default:
       return fail(BES_E_UNSUPPORTED, "no kernel template evaluates this plan (dtype " +
                                          std::string(bes::dtype_name(p.spec.dtype)) + ")");
   }
+}
+
+int bes_plan_set_output(bes_plan *plan, int32_t slot, int64_t offset, const int64_t *strides,
+                        int32_t accumulate) {
+  if (!plan) return fail(BES_E_INVALID, "NULL plan");
+  bes::Plan &p = plan->p;
+  if (slot < 0 || slot >= p.n_slots) return fail(BES_E_INVALID, "slot out of range");
+  if (offset < 0) return fail(BES_E_INVALID, "negative offset");
+  bes::OutLayout L;
+  L.accumulate = accumulate != 0;
+  if (strides || offset) {
+    L.custom = true;
+    L.offset = offset;
+    const std::vector<int64_t> dense = bes::dense_out_strides(p);
+    for (size_t d = 0; d < p.spec.out.size(); ++d) L.stride[d] = strides ? strides[d] : dense[d];
+  }
+  p.out_layout[slot] = L;
+  return BES_OK;
+}
+
+int bes_fill_zero(void *ptr, int64_t n, int32_t dtype, void *hip_stream) {
+  if (n < 0 || (n > 0 && !ptr)) return fail(BES_E_INVALID, "bad buffer");
+  int bytes = dtype == BES_FLOAT64 ? 8 : dtype == BES_FLOAT32 ? 4 : 0;
+  if (!bytes) return fail(BES_E_UNSUPPORTED, "fill supports float32 and float64");
+  hipError_t e = bes::launch_fill_zero(ptr, n, bytes, (hipStream_t)hip_stream);
+  return e == hipSuccess ? BES_OK : hip_fail(e, "fill");
 }
 
 // ---------------------------------------------------------------------------

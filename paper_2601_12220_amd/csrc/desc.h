@@ -113,7 +113,14 @@ typedef struct GenEinsum {
   int32_t row_dep;                       // bit k: operand k carries a shared index
   int32_t split;                         // chunks of the shared space per output
                                          // (> 1: chunks add into zeroed outputs)
-  int64_t ostride[BES_GEN_MAX_IDX];
+  // Output slot s is written at o_off[s] + sum_d idx_d * o_str[s][d] (dense
+  // row-major unless the caller set a layout); o_acc[s] != 0 adds into it
+  // (atomically: slots may share memory).
+  int64_t o_off[BES_GEN_MAX_B];
+  int64_t o_str[BES_GEN_MAX_B][BES_GEN_MAX_IDX];
+  int32_t o_acc[BES_GEN_MAX_B];
+  int32_t o_dense;                       // every slot dense, offset 0, overwrite
+  int32_t pad3;
   int32_t layout[BES_GEN_MAX_B][BES_GEN_MAX_OPS];  // layout id per (member, op)
   int32_t slot_of[BES_GEN_MAX_B];                  // member -> output slot
   int32_t slot_m0[BES_GEN_MAX_B], slot_m1[BES_GEN_MAX_B];  // members of slot,
@@ -157,6 +164,8 @@ typedef struct MfmaSlot {
   float *C;
   int64_t scm, scn;
   int32_t m0, m1;     // members [m0, m1) are summed into C
+  int32_t acc;        // add into C instead of overwriting it
+  int32_t pad;
 } MfmaSlot;
 
 typedef struct MfmaArgs {

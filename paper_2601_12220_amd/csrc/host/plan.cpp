@@ -215,15 +215,11 @@ bool merge_group(const Plan &p, int arg, int j, const std::vector<int> &grp,
   return true;
 }
 
-bool merge_out(const std::vector<int> &out, const std::vector<int> &grp,
-               const std::vector<int64_t> &ext, int64_t &stride) {
-  // dense row-major output strides in `out` order
-  std::vector<int64_t> st(out.size());
-  int64_t s = 1;
-  for (int d = (int)out.size() - 1; d >= 0; --d) {
-    st[d] = s;
-    s *= ext[out[d]];
-  }
+// Merged stride of an index group in an output with strides `st` along
+// `out`; false if the group does not merge into one strided axis.
+bool merge_out_strided(const std::vector<int> &out, const std::vector<int64_t> &st,
+                       const std::vector<int> &grp, const std::vector<int64_t> &ext,
+                       int64_t &stride) {
   auto sof = [&](int c) {
     for (size_t d = 0; d < out.size(); ++d)
       if (out[d] == c) return st[d];
@@ -358,6 +354,37 @@ bes_config default_config(const Plan &p) {
   return c;
 }
 
+std::vector<int64_t> dense_out_strides(const Plan &p) {
+  const Spec &s = p.spec;
+  std::vector<int64_t> st(s.out.size());
+  int64_t v = 1;
+  for (int d = (int)s.out.size() - 1; d >= 0; --d) {
+    st[d] = v;
+    v *= s.extent[s.out[d]];
+  }
+  return st;
+}
+
+std::vector<int64_t> out_strides(const Plan &p, int slot) {
+  if (slot < (int)p.out_layout.size() && p.out_layout[slot].custom) {
+    const OutLayout &L = p.out_layout[slot];
+    return std::vector<int64_t>(L.stride, L.stride + p.spec.out.size());
+  }
+  return dense_out_strides(p);
+}
+
+bool outputs_plain(const Plan &p) {
+  for (const OutLayout &L : p.out_layout)
+    if (L.custom || L.accumulate) return false;
+  return true;
+}
+
+bool any_accumulate(const Plan &p) {
+  for (const OutLayout &L : p.out_layout)
+    if (L.accumulate) return true;
+  return false;
+}
+
 int build_plan(Plan &p, std::string &err) {
   int rc = canonicalize(p.spec, p.canon, err);
   if (rc) return rc;
@@ -368,6 +395,7 @@ int build_plan(Plan &p, std::string &err) {
     for (int i = 0; i < p.spec.b; ++i) p.slot_of_member[i] = i;
     p.n_slots = p.spec.b;
   }
+  p.out_layout.assign(p.n_slots, OutLayout());
   p.src_base.resize(p.spec.args.size());
   p.n_src = 0;
   for (size_t a = 0; a < p.spec.args.size(); ++a) {
@@ -444,20 +472,11 @@ int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a
   }
   a.n_groups = (int)keys.size();
   a.n_members = e.b;
-  // output dense row-major strides along (e, x, i)
-  std::vector<int64_t> ost(e.out.size());
-  {
-    int64_t s = 1;
-    for (int d = (int)e.out.size() - 1; d >= 0; --d) {
-      ost[d] = s;
-      s *= e.extent[e.out[d]];
-    }
+  if (any_accumulate(p)) {
+    err = "the FEM-stream template overwrites its outputs";
+    return BES_E_UNSUPPORTED;
   }
-  auto ostride = [&](int c) -> int64_t {
-    for (size_t d = 0; d < e.out.size(); ++d)
-      if (e.out[d] == c) return ost[d];
-    return 0;
-  };
+  const int64_t item = p.spec.dtype == BES_FLOAT64 ? 8 : 4;
   int m = 0;
   for (int g = 0; g < a.n_groups; ++g) {
     FemGroup &G = a.grp[g];
@@ -484,7 +503,17 @@ int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a
         std::memset(&M.g, 0, sizeof M.g);
         M.g.kind = FEM_SRC_NONE;
       }
-      M.out = out[p.slot_of_member[p.canon.member_map[k]]];
+      // Output strides along (e, x, i): the canonical output axes are the
+      // caller's output axes in the same order, renamed.
+      const int slot = p.slot_of_member[p.canon.member_map[k]];
+      const std::vector<int64_t> ost = out_strides(p, slot);
+      auto ostride = [&](int c) -> int64_t {
+        for (size_t d = 0; d < e.out.size(); ++d)
+          if (e.out[d] == c) return ost[d];
+        return 0;
+      };
+      M.out = (char *)out[slot] +
+              (p.out_layout[slot].custom ? p.out_layout[slot].offset * item : 0);
       M.oe = ostride(R.e);
       M.ox = R.x >= 0 ? ostride(R.x) : 0;
       M.oi = ostride(R.i);
@@ -580,8 +609,15 @@ int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std:
   g.out_size = 1;
   for (int d = g.n_out - 1; d >= 0; --d) {
     g.out_ext[d] = s.extent[s.out[d]];
-    g.ostride[d] = g.out_size;
     g.out_size *= g.out_ext[d];
+  }
+  g.o_dense = outputs_plain(p) ? 1 : 0;
+  for (int sl = 0; sl < p.n_slots; ++sl) {
+    std::vector<int64_t> st = out_strides(p, sl);
+    for (int d = 0; d < g.n_out; ++d) g.o_str[sl][d] = st[d];
+    const OutLayout *L = sl < (int)p.out_layout.size() ? &p.out_layout[sl] : nullptr;
+    g.o_off[sl] = L && L->custom ? L->offset : 0;
+    g.o_acc[sl] = L && L->accumulate ? 1 : 0;
   }
   g.con_size = 1;
   for (int d = 0; d < g.n_con; ++d) {
@@ -703,10 +739,15 @@ int bind_mfma(const Plan &p, const void *const *src, void *const *out, MfmaArgs 
   int m = 0;
   for (int sl = 0; sl < p.n_slots; ++sl) {
     MfmaSlot &S = a.slot[sl];
-    S.C = (float *)out[sl];
+    S.C = (float *)out[sl] + (p.out_layout[sl].custom ? p.out_layout[sl].offset : 0);
+    S.acc = p.out_layout[sl].accumulate ? 1 : 0;
     int64_t cm, cn;
-    merge_out(e.out, R.Mi, e.extent, cm);
-    merge_out(e.out, R.Ni, e.extent, cn);
+    const std::vector<int64_t> ost = out_strides(p, sl);
+    if (!merge_out_strided(e.out, ost, R.Mi, e.extent, cm) ||
+        !merge_out_strided(e.out, ost, R.Ni, e.extent, cn)) {
+      err = "output layout does not merge the M and N index groups";
+      return BES_E_UNSUPPORTED;
+    }
     S.scm = cm;
     S.scn = cn;
     S.m0 = m;

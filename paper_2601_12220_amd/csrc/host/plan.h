@@ -29,6 +29,32 @@ struct MfmaRoles {
   int64_t M = 0, N = 0, K = 0;
 };
 
+// Where a launch writes output slot s: element offset and strides along the
+// output indices in the notation's output order, and whether it adds into the
+// existing values.  Default: offset 0, dense row-major, overwrite.
+struct OutLayout {
+  bool custom = false;      // false: dense row-major, offset 0
+  int64_t offset = 0;
+  int64_t stride[BES_MAX_DIM] = {0};
+  bool accumulate = false;
+};
+
+inline bool same_layout(const OutLayout &a, const OutLayout &b) {
+  if (a.custom != b.custom || a.accumulate != b.accumulate) return false;
+  if (!a.custom) return true;
+  if (a.offset != b.offset) return false;
+  for (int d = 0; d < BES_MAX_DIM; ++d)
+    if (a.stride[d] != b.stride[d]) return false;
+  return true;
+}
+
+inline bool same_layouts(const std::vector<OutLayout> &a, const std::vector<OutLayout> &b) {
+  if (a.size() != b.size()) return false;
+  for (size_t k = 0; k < a.size(); ++k)
+    if (!same_layout(a[k], b[k])) return false;
+  return true;
+}
+
 struct Plan {
   Spec spec;
   Canonical canon;
@@ -53,14 +79,24 @@ struct Plan {
   // For adjoint plans: this plan's flat source k is the caller's src_from[k].
   std::vector<int> src_from;
   bool adjoint = false;
+  // Output layouts per slot (bes_plan_set_output).
+  std::vector<OutLayout> out_layout;
 
   // FEM-stream workspace for the packed shared operand (first FEM launch).
   mutable void *fem_ws = nullptr;
   mutable int fem_ws_device = -1;
-  // Device copy of the generic descriptor (created on first generic launch).
-  mutable void *gen_dev = nullptr;
-  mutable int gen_dev_device = -1;
-  mutable bes_config gen_dev_cfg{};
+  // Generic descriptors bound so far, one per (config, output layouts,
+  // device): a pinned host copy and the device copy uploaded from it.  Kept
+  // until the plan is destroyed, so a launch never waits for or frees a
+  // descriptor an earlier launch may still read.
+  struct GenCopy {
+    bes_config cfg{};
+    std::vector<OutLayout> layouts;
+    int device = -1;
+    GenEinsum *host = nullptr;   // pinned
+    GenEinsum *dev = nullptr;
+  };
+  mutable std::vector<GenCopy> gen_cache;
   // Profiling hook (bes_plan_set_timing): events recorded around the main
   // evaluation kernel(s) of every launch; caller-owned hipEvent_t handles.
   void *time_start = nullptr;
@@ -82,6 +118,14 @@ int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std:
 int bind_generic_ptrs(const Plan &p, const void *const *src, void *const *out, GenPtrs &ptrs);
 int bind_mfma(const Plan &p, const void *const *src, void *const *out, MfmaArgs &a,
               std::string &err);
+
+// Dense row-major strides of the output in the notation's order.
+std::vector<int64_t> dense_out_strides(const Plan &p);
+// Strides of slot `slot` along the user's output indices (custom or dense).
+std::vector<int64_t> out_strides(const Plan &p, int slot);
+// True when no slot has a custom layout or accumulates.
+bool outputs_plain(const Plan &p);
+bool any_accumulate(const Plan &p);
 
 // Build the adjoint plan of position `pos` (see bes_adjoint in bes.h).
 int build_adjoint(const Plan &fwd, int pos, Plan &adj, int &n_out, std::string &err);

@@ -166,8 +166,15 @@ __device__ void gen_tile(const GenEinsum *__restrict__ G, const GenPtrs *__restr
     }
     for (int off = lanes >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (active && sub == 0) {
-      if (split > 1) atomicAdd(&outp[o], acc);   // chunks meet in the zeroed output
-      else outp[o] = acc;
+      int64_t oa = o;
+      if (!G->o_dense) {
+        oa = G->o_off[slot];
+        for (int d = 0; d < n_out; ++d) oa += oidx[d] * G->o_str[slot][d];
+      }
+      // chunks meet in the zeroed output; accumulating slots add into the
+      // caller's values (atomically: several slots may address one buffer)
+      if (split > 1 || G->o_acc[slot]) atomicAdd(&outp[oa], acc);
+      else outp[oa] = acc;
     }
   }
 }
@@ -188,26 +195,43 @@ __global__ void __launch_bounds__(256) generic_kernel(const GenEinsum *__restric
   gen_tile<T>(G, &P, slot, first, count, chunk);
 }
 
-// Zero the outputs of split einsums (chunks add into them).  Block row
-// blockIdx.y is the einsum; grid-stride over its slots' outputs.
+// Address of output element o (linear in the output's index order) of slot
+// s under the slot's layout.
+__device__ __forceinline__ int64_t gen_out_addr(const GenEinsum &G, int s, int64_t o) {
+  if (G.o_dense) return o;
+  int64_t a = G.o_off[s], rem = o;
+  for (int d = G.n_out - 1; d >= 0; --d) {
+    const int64_t c = rem % G.out_ext[d];
+    rem /= G.out_ext[d];
+    a += c * G.o_str[s][d];
+  }
+  return a;
+}
+
+// Zero the overwritten outputs of a split einsum (its chunks add into them).
 template <typename T>
-__global__ void __launch_bounds__(256) zero_split_outputs(const GenEinsum *__restrict__ table,
-                                                          const GenPtrs *__restrict__ ptrs) {
-  const GenEinsum &G = table[blockIdx.y];
+__device__ void zero_slots(const GenEinsum &G, const GenPtrs &P) {
   if (G.split <= 1) return;
   const int64_t total = G.out_size * G.n_slots;
   for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < total;
        f += (int64_t)gridDim.x * blockDim.x) {
     const int s = (int)(f / G.out_size);
-    ((T *)ptrs[blockIdx.y].out[s])[f - s * G.out_size] = (T)0;
+    if (G.o_acc[s]) continue;
+    ((T *)P.out[s])[gen_out_addr(G, s, f - s * G.out_size)] = (T)0;
   }
 }
 
+// Block row blockIdx.y is the einsum of the persistent table.
 template <typename T>
-__global__ void __launch_bounds__(256) fill_zero(T *__restrict__ p, int64_t n) {
-  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n;
-       f += (int64_t)gridDim.x * blockDim.x)
-    p[f] = (T)0;
+__global__ void __launch_bounds__(256) zero_split_outputs(const GenEinsum *__restrict__ table,
+                                                          const GenPtrs *__restrict__ ptrs) {
+  zero_slots<T>(table[blockIdx.y], ptrs[blockIdx.y]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) zero_split_one(const GenEinsum *__restrict__ G,
+                                                      const GenPtrs P) {
+  zero_slots<T>(*G, P);
 }
 
 template <typename T>
@@ -235,7 +259,26 @@ __global__ void __launch_bounds__(256) persistent_kernel(const GenEinsum *__rest
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) fill_zero(T *__restrict__ p, int64_t n) {
+  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n;
+       f += (int64_t)gridDim.x * blockDim.x)
+    p[f] = (T)0;
+}
+
 }  // namespace
+
+hipError_t launch_fill_zero(void *p, int64_t n, int elem_bytes, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(fill_zero<double>, dim3(g), dim3(256), 0, stream, (double *)p, n);
+  else if (elem_bytes == 4)
+    hipLaunchKernelGGL(fill_zero<float>, dim3(g), dim3(256), 0, stream, (float *)p, n);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 hipError_t launch_generic(bool f64, const GenEinsum *dev, const GenEinsum &host,
                           const GenPtrs &ptrs, hipStream_t stream) {
@@ -244,16 +287,12 @@ hipError_t launch_generic(bool f64, const GenEinsum *dev, const GenEinsum &host,
   const int64_t blocks = tiles * host.n_slots * (host.split > 1 ? host.split : 1);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   if (host.split > 1) {
-    // one-einsum "table": the device descriptor and a device copy of ptrs
-    // are not at hand here, so the zeroing runs per slot with the host ptrs
-    for (int s = 0; s < host.n_slots; ++s) {
-      const int64_t n = host.out_size;
-      const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
-      if (f64)
-        hipLaunchKernelGGL(fill_zero<double>, dim3(g), dim3(256), 0, stream, (double *)ptrs.out[s], n);
-      else
-        hipLaunchKernelGGL(fill_zero<float>, dim3(g), dim3(256), 0, stream, (float *)ptrs.out[s], n);
-    }
+    const int64_t n = host.out_size * host.n_slots;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    if (f64)
+      hipLaunchKernelGGL(zero_split_one<double>, dim3(g), dim3(256), 0, stream, dev, ptrs);
+    else
+      hipLaunchKernelGGL(zero_split_one<float>, dim3(g), dim3(256), 0, stream, dev, ptrs);
   }
   dim3 grid((unsigned)blocks), block(256);
   if (f64)

@@ -38,7 +38,13 @@ hipError_t launch_persistent(bool f64, const GenEinsum *table, const GenPtrs *pt
                              const GenItem *items, int n_items, unsigned *counters,
                              int grid, hipStream_t stream, int n_einsums, bool any_split);
 
-// MFMA dense-contraction template (FP32).
+// Zero n elements of 4 or 8 bytes at p (a fill kernel: no memset node, so a
+// captured graph replays it correctly).
+hipError_t launch_fill_zero(void *p, int64_t n, int elem_bytes, hipStream_t stream);
+
+// MFMA dense-contraction template (FP32).  mfma_args_ok: the shape and the
+// alignment of every operand fit the template's vector tile loads.
+bool mfma_args_ok(const MfmaArgs &a);
 hipError_t launch_mfma(const MfmaArgs &a, int tile_m, int tile_n, hipStream_t stream);
 
 }  // namespace bes

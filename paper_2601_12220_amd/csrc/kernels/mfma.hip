@@ -180,18 +180,28 @@ __global__ void __launch_bounds__(256) mfma_gemm_kernel(const MfmaArgs a, int ti
     }
     __syncthreads();
   }
-  // D[i][j] of a 16x16 tile sits in lane j + 16 * (i / 4), register i % 4.
+  // D[i][j] of a 16x16 tile sits in lane j + 16 * (i / 4), register i % 4:
+  // each lane holds 4 consecutive m of one n.  With C contiguous along m
+  // (a permuted output layout) those 4 values are one 16-byte store.
   float *__restrict__ C = S.C;
+  const bool vec_m = S.scm == 1 && (S.scn & 3) == 0 && ((uintptr_t)C & 15) == 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      const int64_t mb = m0 + wm * 64 + i * 16 + 4 * (lane >> 4);
+      const int64_t n = n0 + wn * 64 + j * 16 + (lane & 15);
+      if (vec_m) {
+        floatx4 *p = (floatx4 *)(C + mb + n * S.scn);
+        *p = S.acc ? *p + acc[i][j] : acc[i][j];
+      } else {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + c;
-        const int64_t n = n0 + wn * 64 + j * 16 + (lane & 15);
-        C[m * S.scm + n * S.scn] = acc[i][j][c];
+        for (int c = 0; c < 4; ++c) {
+          float *p = C + (mb + c) * S.scm + n * S.scn;
+          *p = S.acc ? *p + acc[i][j][c] : acc[i][j][c];
+        }
       }
+    }
 }
 
 }  // namespace
@@ -201,18 +211,21 @@ bool mfma_shape_ok(int64_t M, int64_t N, int64_t K) {
          (M / BM) * (N / BN) <= (1 << 24);
 }
 
-hipError_t launch_mfma(const MfmaArgs &a, int /*tile_m*/, int /*tile_n*/, hipStream_t stream) {
-  if (!mfma_shape_ok(a.M, a.N, a.K) || a.n_slots < 1) return hipErrorInvalidValue;
+bool mfma_args_ok(const MfmaArgs &a) {
+  if (!mfma_shape_ok(a.M, a.N, a.K) || a.n_slots < 1) return false;
   for (int m = 0; m < a.n_members; ++m) {
     const MfmaMember &mb = a.mem[m];
     // vector loads need 16-byte aligned rows along the contiguous direction
-    if (mb.sak == 1 && (mb.sam % 4 || ((uintptr_t)mb.A & 15))) return hipErrorInvalidValue;
-    if (mb.sak != 1 && mb.sam == 1 && (mb.sak % 4 || ((uintptr_t)mb.A & 15)))
-      return hipErrorInvalidValue;
-    if (mb.sbn == 1 && (mb.sbk % 4 || ((uintptr_t)mb.B & 15))) return hipErrorInvalidValue;
-    if (mb.sbn != 1 && mb.sbk == 1 && (mb.sbn % 4 || ((uintptr_t)mb.B & 15)))
-      return hipErrorInvalidValue;
+    if (mb.sak == 1 && (mb.sam % 4 || ((uintptr_t)mb.A & 15))) return false;
+    if (mb.sak != 1 && mb.sam == 1 && (mb.sak % 4 || ((uintptr_t)mb.A & 15))) return false;
+    if (mb.sbn == 1 && (mb.sbk % 4 || ((uintptr_t)mb.B & 15))) return false;
+    if (mb.sbn != 1 && mb.sbk == 1 && (mb.sbn % 4 || ((uintptr_t)mb.B & 15))) return false;
   }
+  return true;
+}
+
+hipError_t launch_mfma(const MfmaArgs &a, int /*tile_m*/, int /*tile_n*/, hipStream_t stream) {
+  if (!mfma_args_ok(a)) return hipErrorInvalidValue;
   const int tm = (int)(a.M / BM), tn = (int)(a.N / BN);
   dim3 grid((unsigned)(tm * tn * a.n_slots));
   hipLaunchKernelGGL(mfma_gemm_kernel, grid, dim3(256), 0, stream, a, tm, tn);

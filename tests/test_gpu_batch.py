@@ -112,3 +112,58 @@ def test_batch_with_new_output_buffers(batch_setup):
         for k in range(6):
             for m in range(ws[k].b):
                 assert rel_fro(outs[k][m].double().cpu().numpy(), refs[k][m]) <= TOL["float32"]
+
+
+# ---------------------------------------------------------------------------
+# The batch exactly as the benchmark times it: all 256 batched einsums (64 of
+# them renamed / permuted variants), tuned with the benchmark's settings, then
+# one persistent replay.  Every output is compared with the FP64 oracle and
+# with one plain launch per batched einsum under the same tuned configs
+# (including the split configs whose chunks add into zeroed outputs).
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def benched_batch(tmp_path_factory):
+    ws = workloads.config4()
+    ctx = Context(str(tmp_path_factory.mktemp("db256") / "tuning.db"))
+    plans = [ctx.register(w.notation, w.table, w.operands) for w in ws]
+    bufs = [device_buffers(w) for w in ws]
+    _say(f"[batch256] oracle for {len(ws)} batched einsums")
+    refs = [oracle_full(w) for w in ws]
+    return ws, ctx, plans, bufs, refs
+
+
+def test_benched_256_batch_matches_oracle_and_plain(benched_batch):
+    ws, ctx, plans, bufs, refs = benched_batch
+    assert len(ws) == 256
+    stream = torch.cuda.Stream()
+    _say("[batch256] tuning as the benchmark does (reps=3, warmup=1)")
+    with torch.cuda.stream(stream):
+        results, hits = tune.tune_all(ctx, [(p, b, _nan_outputs(w))
+                                            for p, b, w in zip(plans, bufs, ws)],
+                                      stream=stream, reps=3, warmup=1)
+    torch.cuda.synchronize()
+    n_var = sum(w.info["variant_of"] is not None for w in ws)
+    assert n_var == 64 and hits >= n_var
+    splits = sum(1 for p in plans if p.config.template_id == tune.T_GENERIC and p.config.p[2] > 1)
+    _say(f"[batch256] {len(results)} tuned records, {hits} retrievals, {splits} split configs")
+    batch = Batch(ctx, plans)
+    outs_b = [_nan_outputs(w) for w in ws]
+    outs_p = [_nan_outputs(w) for w in ws]
+    sh = int(stream.cuda_stream)
+    srcs = [p.src_ptrs(b) for p, b in zip(plans, bufs)]
+    batch.launch_ptrs(srcs, [[o.data_ptr() for o in os_] for os_ in outs_b], sh)
+    for p, s, os_ in zip(plans, srcs, outs_p):
+        p.launch_ptrs(s, [o.data_ptr() for o in os_], sh)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, w in enumerate(ws):
+        for m in range(w.b):
+            got_b = outs_b[k][m].double().cpu().numpy()
+            got_p = outs_p[k][m].double().cpu().numpy()
+            eb = rel_fro(got_b, refs[k][m])
+            worst = max(worst, eb)
+            assert eb <= TOL["float32"], (k, w.notation, m, eb, plans[k].config.p[:3])
+            assert rel_fro(got_p, refs[k][m]) <= TOL["float32"], (k, w.notation, m)
+            assert rel_fro(got_b, got_p) <= TOL["float32"], (k, m)
+    _say(f"[batch256] worst relative Frobenius error vs oracle {worst:.3e}")

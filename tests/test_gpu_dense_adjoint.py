@@ -148,3 +148,90 @@ def test_fem_adjoint_matches_oracle(ctx):
         refu += oracle.einsum_grad(n, ops, g[x], 2)
     for got, ref in ((gJ, refJ), (gD, refD), (gu, refu)):
         assert rel_fro(got.cpu().numpy(), ref) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Gradient sums and view scatters inside the library: a buffer read at two
+# operand positions (the second adjoint adds into what the first wrote), a
+# view covering part of its buffer (zeroed gradient, then added into), and
+# views of one buffer that overlap inside one adjoint launch (atomic adds).
+# ---------------------------------------------------------------------------
+
+def _op(name, shape, dtype, kind="array", src=None, offset=0, strides=None):
+    return workloads.Operand(name, tuple(shape), dtype, kind, (src or name,),
+                             offset=offset, strides=strides)
+
+
+def _oracle_grads(notation, table, operands, vals, G, buffers):
+    """d<G, R>/d(buffer) from the oracle's definitional gradient, scattered
+    through each argument's view (numpy, FP64)."""
+    out = {b: np.zeros(buffers[b].numel()) for b in buffers}
+    for i, row in enumerate(table):
+        for pos, a in enumerate(row):
+            o = operands[a]
+            g = oracle.einsum_grad(notation, [vals[x] for x in row], G[i], pos)
+            if o.kind == "view":
+                idx = np.full((), o.offset, dtype=np.int64)
+                for ext, st in zip(o.shape, o.strides):
+                    idx = np.add.outer(idx, np.arange(ext) * st)
+                np.add.at(out[o.sources[0]], idx.ravel(), g.ravel())
+            else:
+                out[o.sources[0]] += g.ravel()
+    return out
+
+
+@pytest.mark.parametrize("case", ["square_AA_mfma", "square_AA_fp64", "partial_view",
+                                  "overlapping_views"])
+def test_gradient_sums_and_scatters_in_library(ctx, case):
+    gen = torch.Generator().manual_seed(2601_12220 + 900)
+    if case.startswith("square_AA"):
+        # R = A A (A at both positions): dA = G A^T + A^T G
+        dt = "float32" if case.endswith("mfma") else "float64"
+        n = 128 if dt == "float32" else 24
+        bufs = {"A": torch.randn(n, n, generator=gen, dtype=torch.float64).to(
+            torch.float32 if dt == "float32" else torch.float64)}
+        operands = {"A": _op("A", (n, n), dt)}
+        notation, table = "ik,kj->ij", [["A", "A"]]
+    elif case == "partial_view":
+        # two members read disjoint row blocks of X that leave rows uncovered
+        dt = "float64"
+        bufs = {"X": torch.randn(40, 6, generator=gen, dtype=torch.float64),
+                "B": torch.randn(6, 5, generator=gen, dtype=torch.float64)}
+        operands = {"X0": _op("X0", (8, 6), dt, "view", "X", 0, (6, 1)),
+                    "X1": _op("X1", (8, 6), dt, "view", "X", 12 * 6, (6, 1)),
+                    "B": _op("B", (6, 5), dt)}
+        notation, table = "ik,kj->ij", [["X0", "B"], ["X1", "B"]]
+    else:
+        # overlapping views of one buffer at one position: one adjoint launch
+        # adds both slots into the same memory
+        dt = "float64"
+        bufs = {"X": torch.randn(30, 4, generator=gen, dtype=torch.float64),
+                "B": torch.randn(4, 7, generator=gen, dtype=torch.float64)}
+        operands = {"X0": _op("X0", (20, 4), dt, "view", "X", 0, (4, 1)),
+                    "X1": _op("X1", (20, 4), dt, "view", "X", 5 * 4, (4, 1)),
+                    "B": _op("B", (4, 7), dt)}
+        notation, table = "ik,kj->ij", [["X0", "B"], ["X1", "B"]]
+    be = BatchedEinsum(ctx, notation, table, operands)
+    _say(f"[grad-sum] {case}: adjoint templates "
+         f"{[be.adjoint(p).template for p in range(2)]}")
+    leaves = {k: v.cuda().requires_grad_(True) for k, v in bufs.items()}
+    outs = be(leaves)
+    G = [torch.randn(o.shape, generator=gen, dtype=torch.float64).to(o.dtype).cuda()
+         for o in outs]
+    grads = torch.autograd.grad(outs, [leaves[k] for k in sorted(leaves)], G)
+    torch.cuda.synchronize()
+    vals = {a: (F_view(bufs[o.sources[0]].double().numpy(), o)) for a, o in operands.items()}
+    ref = _oracle_grads(notation, table, operands, vals,
+                        [g.double().cpu().numpy() for g in G], bufs)
+    tol = TOL[dt]
+    for k, g in zip(sorted(leaves), grads):
+        err = rel_fro(g.double().cpu().numpy().ravel(), ref[k])
+        _say(f"[grad-sum] {case} d{k} rel_fro={err:.2e}")
+        assert err <= tol, (case, k, err)
+
+
+def F_view(buf, o):
+    from oracle import functional as F
+    if o.kind == "view":
+        return F.strided_view(buf.ravel(), o.shape, o.strides, o.offset)
+    return buf.reshape(o.shape)

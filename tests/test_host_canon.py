@@ -484,3 +484,27 @@ def test_generic_default_lanes_follow_the_contraction(ctx):
         p = ctx.register("ab,b->a", [["A", "B"]], ops)
         assert p.template == "generic"
         assert p.config.p[1] == lanes, (k, p.config.p[1])
+
+
+def test_functional_source_gradient_is_refused():
+    # asking for the gradient of a buffer behind an element-wise operand
+    # fails loudly in forward, before anything is launched (no GPU needed)
+    import torch
+    from paper_2601_12220_amd import Context
+    from paper_2601_12220_amd.autograd import BatchedEinsum
+    w = workloads.config3(e=64)
+    be = BatchedEinsum(Context(), w.notation, w.table, w.operands)
+    bufs = {k: v.clone().requires_grad_(k.startswith("a")) for k, v in w.buffers.items()}
+    with pytest.raises(ValueError, match="element-wise or tetrahedron-Jacobian"):
+        be(bufs)
+
+
+def test_set_output_validates_slot():
+    from paper_2601_12220_amd import Context, capi
+    w = workloads.config1()
+    p = Context().register(w.notation, w.table, w.operands)
+    capi.bes_plan_set_output(p.h, 2, 0, [10, 1], True)
+    with pytest.raises(capi.BesError):
+        capi.bes_plan_set_output(p.h, 3)
+    with pytest.raises(capi.BesError):
+        capi.bes_plan_set_output(p.h, 0, -1)
