@@ -217,6 +217,22 @@ int bes_ctx_stats(const bes_ctx *ctx, int64_t *hits, int64_t *misses);
 int bes_launch(const bes_plan *plan, const void *const *src_ptrs,
                void *const *out_ptrs, void *hip_stream);
 
+/* bes_launch for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and stream semantics as bes_launch, but it calls no
+ * hipMalloc, hipFree or allocating library routine: the FEM-stream
+ * template's re-laid shared operand goes to a fixed 256 KiB device array
+ * that the library holds on every GPU it runs on until the process ends
+ * (enough for every compiled FEM shape with up to 8 stage-1 groups).  Only
+ * plans whose current template is FEM-stream or MFMA are accepted; others,
+ * a shared operand larger than the array, an accumulating FEM output and
+ * MFMA operands unaligned for its vector tiles give BES_E_UNSUPPORTED
+ * (bes_launch evaluates those).  Calls on one GPU share its array: calls
+ * that overlap in time on one GPU (on different streams, or from several
+ * host threads) race; calls ordered on one stream do not. */
+int bes_launch_noalloc(const bes_plan *plan, const void *const *src_ptrs,
+                       void *const *out_ptrs, void *hip_stream);
+
 /* Output layout of output slot `slot` (0 .. number of outputs - 1: the b
  * members of a plain plan in user order, the n_out outputs of an adjoint
  * plan).  The launch writes element (i_1, ..., i_k) of that output, indices

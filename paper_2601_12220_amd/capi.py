@@ -110,6 +110,7 @@ def load():
         "bes_adjoint": ([P, P, i32, PP, i32p], i32),
         "bes_plan_set_output": ([P, i32, ctypes.c_int64, i64p, i32], i32),
         "bes_fill_zero": ([P, ctypes.c_int64, i32, P], i32),
+        "bes_launch_noalloc": ([P, PP, PP, P], i32),
         "bes_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -261,6 +262,11 @@ def bes_plan_set_timing(h, start_event: int, stop_event: int) -> None:
 def bes_launch(h, src_ptrs, out_ptrs, stream: int = 0) -> None:
     check(load().bes_launch(h, _ptrs(src_ptrs), _ptrs(out_ptrs), ctypes.c_void_p(stream)),
           "bes_launch")
+
+
+def bes_launch_noalloc(h, src_ptrs, out_ptrs, stream: int = 0) -> None:
+    check(load().bes_launch_noalloc(h, _ptrs(src_ptrs), _ptrs(out_ptrs), ctypes.c_void_p(stream)),
+          "bes_launch_noalloc")
 
 
 def bes_batch_create(ctx, plans):

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -169,6 +170,32 @@ int hip_fail(hipError_t e, const char *what) {
   return fail(BES_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Scratch of the entry point that allocates nothing (bes_launch_noalloc): a
+// fixed device array per GPU holding the re-laid shared operand of the
+// FEM-stream template.  In host code `scratch` names a host-side stand-in;
+// kernels get the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device.
+constexpr size_t kScratchBytes = 256 * 1024;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+int scratch_of_current_device(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(BES_E_UNSUPPORTED, "device ordinal >= 64");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BES_OK;
+}
 
 }  // namespace
 
@@ -416,6 +443,59 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
     default:
       return fail(BES_E_UNSUPPORTED, "no kernel template evaluates this plan (dtype " +
                                          std::string(bes::dtype_name(p.spec.dtype)) + ")");
+  }
+}
+
+int bes_launch_noalloc(const bes_plan *plan, const void *const *src_ptrs, void *const *out_ptrs,
+                       void *hip_stream) {
+  if (!plan || !src_ptrs || !out_ptrs) return fail(BES_E_INVALID, "NULL argument");
+  const bes::Plan &p = plan->p;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  std::vector<const void *> src(p.n_src);
+  for (int k = 0; k < p.n_src; ++k) src[k] = p.adjoint ? src_ptrs[p.src_from[k]] : src_ptrs[k];
+  const bool f64 = p.spec.dtype == BES_FLOAT64;
+  std::string err;
+  hipError_t e;
+  auto record = [&](void *ev) -> hipError_t {
+    return ev ? hipEventRecord((hipEvent_t)ev, stream) : hipSuccess;
+  };
+  switch (p.cfg.template_id) {
+    case BES_T_FEM_STREAM: {
+      if (bes::any_accumulate(p))
+        return fail(BES_E_UNSUPPORTED, "no-alloc launch: the FEM-stream template overwrites");
+      const size_t need = bes::fem_workspace_bytes(f64, p.fem.NI, p.fem.NJ, p.fem.NR);
+      if (need > kScratchBytes)
+        return fail(BES_E_UNSUPPORTED, "no-alloc launch: the shared operand needs " +
+                                           std::to_string(need) + " bytes of scratch, more than " +
+                                           std::to_string(kScratchBytes));
+      FemArgs a;
+      int rc = bes::bind_fem(p, src.data(), out_ptrs, a, err);
+      if (rc) return fail(rc, err);
+      void *ws = nullptr;
+      if ((rc = scratch_of_current_device(&ws)) != BES_OK) return rc;
+      e = bes::launch_fem(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, a, ws, p.cfg.p[1],
+                          p.cfg.p[2], stream, (hipEvent_t)p.time_start,
+                          (hipEvent_t)p.time_stop);
+      if (e != hipSuccess) return hip_fail(e, "FEM-stream launch");
+      return BES_OK;
+    }
+    case BES_T_MFMA: {
+      if (accumulating_slots_overlap(p, out_ptrs))
+        return fail(BES_E_UNSUPPORTED, "no-alloc launch: accumulating outputs overlap");
+      MfmaArgs a;
+      int rc = bes::bind_mfma(p, src.data(), out_ptrs, a, err);
+      if (rc) return fail(rc, err);
+      if (!bes::mfma_args_ok(a))
+        return fail(BES_E_UNSUPPORTED, "no-alloc launch: operands unaligned for the MFMA tiles");
+      if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
+      e = bes::launch_mfma(a, p.cfg.p[0], p.cfg.p[1], stream);
+      if (e != hipSuccess) return hip_fail(e, "MFMA launch");
+      if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
+      return BES_OK;
+    }
+    default:
+      return fail(BES_E_UNSUPPORTED,
+                  "no-alloc launch covers the FEM-stream and MFMA templates only");
   }
 }
 
