@@ -400,6 +400,16 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
   switch (p.cfg.template_id) {
     case BES_T_FEM_STREAM: {
       if (bes::any_accumulate(p)) return run_generic(p.cfg);
+      if (p.fem.cls == 1) {
+        FemApplyArgs a;
+        int rc = bes::bind_fem_apply(p, src.data(), out_ptrs, a, err);
+        if (rc) return fail(rc, err);
+        e = bes::launch_fem_apply(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, p.fem.diag, a,
+                                  p.cfg.p[1], stream, (hipEvent_t)p.time_start,
+                                  (hipEvent_t)p.time_stop);
+        if (e != hipSuccess) return hip_fail(e, "FEM-stream apply launch");
+        return BES_OK;
+      }
       FemArgs a;
       int rc = bes::bind_fem(p, src.data(), out_ptrs, a, err);
       if (rc) return fail(rc, err);
@@ -463,6 +473,16 @@ int bes_launch_noalloc(const bes_plan *plan, const void *const *src_ptrs, void *
     case BES_T_FEM_STREAM: {
       if (bes::any_accumulate(p))
         return fail(BES_E_UNSUPPORTED, "no-alloc launch: the FEM-stream template overwrites");
+      if (p.fem.cls == 1) {   // the apply class needs no scratch
+        FemApplyArgs a;
+        int rc = bes::bind_fem_apply(p, src.data(), out_ptrs, a, err);
+        if (rc) return fail(rc, err);
+        e = bes::launch_fem_apply(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, p.fem.diag, a,
+                                  p.cfg.p[1], stream, (hipEvent_t)p.time_start,
+                                  (hipEvent_t)p.time_stop);
+        if (e != hipSuccess) return hip_fail(e, "FEM-stream apply launch");
+        return BES_OK;
+      }
       const size_t need = bes::fem_workspace_bytes(f64, p.fem.NI, p.fem.NJ, p.fem.NR);
       if (need > kScratchBytes)
         return fail(BES_E_UNSUPPORTED, "no-alloc launch: the shared operand needs " +

@@ -71,6 +71,41 @@ typedef struct FemArgs {
 } FemArgs;
 
 // ---------------------------------------------------------------------------
+// FEM-stream "apply" class (face mass and local divergence of Section
+// "Batched einsums in DG-FEM Operators"): per element e and member m,
+//   W_m[c, j]   = sum_x G[x, c, e] U_m[x, e, j]   (DIAG: G[c, e] U_m[c, e, j])
+//   out_m[e, i] = sum_{c, j} S[c, i, j] W_m[c, j]
+// with one S and one G shared by every member (the reference face-mass or
+// derivative matrix and the geometry terms) and a streamed operand U_m per
+// member (flux or vector-field components).  Strides are in elements.
+// ---------------------------------------------------------------------------
+#define BES_FEM_APPLY_MAX_MEMBERS 16
+
+typedef struct FemApplyMember {
+  const void *u0;       // U source 0 (offset applied by the kernel)
+  const void *u1;       // second source of an ELEMENTWISE U, or NULL
+  int64_t uoff0, uoff1;
+  int64_t us0[3];       // U source 0 strides along (x, e, j)
+  int64_t us1[3];       // U source 1 strides along (x, e, j)
+  void *out;
+  int64_t oe, oi;       // output strides along (e, i)
+} FemApplyMember;
+
+typedef struct FemApplyArgs {
+  int64_t E;
+  const void *S;        // offset applied
+  int64_t ss[3];        // S strides along (c, i, j)
+  const void *G;        // offset applied
+  int64_t gs[3];        // G strides along (x, c, e); DIAG: (unused, c, e)
+  int32_t n_members;
+  int32_t u_kind;       // FEM_SRC_ARRAY or FEM_SRC_ELEMENTWISE (all members)
+  int32_t op;           // BES_OP_* of an ELEMENTWISE U
+  int32_t pad;
+  double alpha, beta;
+  FemApplyMember mem[BES_FEM_APPLY_MAX_MEMBERS];
+} FemApplyArgs;
+
+// ---------------------------------------------------------------------------
 // Generic template: any batched einsum with up to 4 operands, 8 output and 8
 // contracted indices.  Output element o of slot s is
 //   sum over members m of slot s, sum over contracted c, prod_k M(A^{m,k})[...]

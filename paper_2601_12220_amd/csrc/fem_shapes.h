@@ -19,3 +19,23 @@ inline bool fem_shape_compiled(bool /*f64*/, int ni, int nj, int nr, int nx) {
 #undef BES_FEM_MATCH
   return false;
 }
+
+// Extents (NI, NJ, NC, NX, DIAG) of the FEM-stream "apply" class: face mass
+// on P1..P4 tetrahedra (i volume DOFs 4/10/20/35, j face DOFs 3/6/10/15,
+// f = 4 faces; the geometry term is diagonal in the face) and local
+// divergence (i = j volume DOFs, r = x = 3).
+#ifndef BES_FEM_APPLY_SHAPES
+#define BES_FEM_APPLY_SHAPES(X)                                            \
+  X(4, 3, 4, 4, true) X(10, 6, 4, 4, true) X(20, 10, 4, 4, true)           \
+  X(35, 15, 4, 4, true)                                                    \
+  X(4, 4, 3, 3, false) X(10, 10, 3, 3, false) X(20, 20, 3, 3, false)       \
+  X(35, 35, 3, 3, false)
+#endif
+
+inline bool fem_apply_shape_listed(int ni, int nj, int nc, int nx, bool diag) {
+#define BES_FEM_APPLY_MATCH(a, b, c, d, g) \
+  if (ni == (a) && nj == (b) && nc == (c) && nx == (d) && diag == (g)) return true;
+  BES_FEM_APPLY_SHAPES(BES_FEM_APPLY_MATCH)
+#undef BES_FEM_APPLY_MATCH
+  return false;
+}

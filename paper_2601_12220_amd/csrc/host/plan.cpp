@@ -56,7 +56,7 @@ int axis_of(const Plan &p, int j, int c) {
   return -1;
 }
 
-void analyse_fem(Plan &p) {
+void analyse_fem_grad(Plan &p) {
   const CanonEinsum &e = p.canon.form;
   auto fail = [&](const char *why) {
     p.fem_ok = false;
@@ -198,6 +198,136 @@ void analyse_fem(Plan &p) {
   p.fem_why.clear();
 }
 
+// The "apply" class of the FEM-stream template (face mass and local
+// divergence, Section "Batched einsums in DG-FEM Operators"): three operands,
+// output (e, i); S[c, i, j] without the stream index; G[x, c, e] (or G[c, e]:
+// diagonal in the component, face mass) and U[x, e, j] (U[c, e, j]) with it.
+// S and G must be the same arguments in every member.
+void analyse_fem_apply(Plan &p) {
+  const CanonEinsum &e = p.canon.form;
+  auto fail = [&](const char *why) {
+    p.fem_ok = false;
+    p.fem_why = std::string("apply class: ") + why;
+  };
+  if (p.adjoint) return fail("adjoint plans sum members");
+  if (p.spec.dtype != BES_FLOAT32 && p.spec.dtype != BES_FLOAT64) return fail("dtype");
+  if (e.b > BES_FEM_APPLY_MAX_MEMBERS) return fail("b > 16");
+  if (e.n != 3) return fail("n != 3");
+  if (e.out.size() != 2) return fail("output must be (e, i)");
+  for (const auto &l : e.ins)
+    if (has_repeat(l)) return fail("repeated index");
+  const int E = e.extent[e.out[0]] > e.extent[e.out[1]] ? e.out[0]
+                : e.extent[e.out[1]] > e.extent[e.out[0]] ? e.out[1] : -1;
+  if (E < 0) return fail("no unique stream index");
+  for (int c = 0; c < (int)e.extent.size(); ++c)
+    if (c != E && e.extent[c] >= e.extent[E]) return fail("no unique stream index");
+  const int I = e.out[0] == E ? e.out[1] : e.out[0];
+  std::vector<int> with_e, without_e;
+  for (int j = 0; j < e.n; ++j) (contains(e.ins[j], E) ? with_e : without_e).push_back(j);
+  if (without_e.size() != 1 || with_e.size() != 2) return fail("need one operand without e");
+  FemRoles R;
+  R.cls = 1;
+  R.e = E;
+  R.i = I;
+  R.posS = without_e[0];
+  const auto &S = e.ins[R.posS];
+  if (S.size() != 3 || !contains(S, I)) return fail("S must be (c, i, j)");
+  std::vector<int> sc;
+  for (int c : S)
+    if (c != I) sc.push_back(c);
+  // Every assignment of (U, G) and (c, j) that matches the pattern; the
+  // divergence pattern is symmetric under (G, c) <-> (U, j), so prefer a G
+  // that all members share, then a compiled instantiation.
+  std::vector<FemRoles> cands;
+  for (int pu = 0; pu < 2; ++pu) {
+    const auto &U = e.ins[with_e[pu]];
+    const auto &G = e.ins[with_e[1 - pu]];
+    if (U.size() != 3 || contains(U, I) || contains(G, I)) continue;
+    for (int t = 0; t < 2; ++t) {
+      const int c = sc[t], j = sc[1 - t];
+      if (!contains(U, j) || contains(G, j) || !contains(G, c)) continue;
+      FemRoles C = R;
+      if (G.size() == 2 && contains(U, c)) {              // G[c, e], U[c, e, j]
+        C.diag = true;
+        C.r = c;
+        C.x = c;
+      } else if (G.size() == 3 && !contains(U, c)) {      // G[x, c, e], U[x, e, j]
+        int x = -1;
+        for (int q : G)
+          if (q != E && q != c) x = q;
+        if (x < 0 || !contains(U, x) || contains(S, x) || contains(e.out, x)) continue;
+        C.diag = false;
+        C.r = c;
+        C.x = x;
+      } else {
+        continue;
+      }
+      C.j = j;
+      C.posU = with_e[pu];
+      C.posG = with_e[1 - pu];
+      C.NI = (int)e.extent[C.i];
+      C.NJ = (int)e.extent[C.j];
+      C.NR = (int)e.extent[C.r];
+      C.NX = (int)e.extent[C.x];
+      cands.push_back(C);
+    }
+  }
+  if (cands.empty()) return fail("operands do not match S[c,i,j], G[x,c,e], U[x,e,j]");
+  auto shared_g = [&](const FemRoles &C) {
+    for (int k = 1; k < e.b; ++k)
+      if (slot_arg(p, k, C.posG) != slot_arg(p, 0, C.posG)) return false;
+    return true;
+  };
+  int best = -1, best_score = -1;
+  for (size_t q = 0; q < cands.size(); ++q) {
+    const FemRoles &C = cands[q];
+    const int score = (shared_g(C) ? 2 : 0) +
+                      (fem_apply_shape_listed(C.NI, C.NJ, C.NR, C.NX, C.diag) ? 1 : 0);
+    if (score > best_score) {
+      best_score = score;
+      best = (int)q;
+    }
+  }
+  R = cands[best];
+  if (!fem_apply_shape_listed(R.NI, R.NJ, R.NR, R.NX, R.diag))
+    return fail("no compiled instantiation for these extents");
+  const int s0 = slot_arg(p, 0, R.posS), g0 = slot_arg(p, 0, R.posG);
+  const int u0 = slot_arg(p, 0, R.posU);
+  const Operand &uo = p.spec.args[u0];
+  for (int k = 0; k < e.b; ++k) {
+    if (slot_arg(p, k, R.posS) != s0 || slot_arg(p, k, R.posG) != g0)
+      return fail("S and G must be shared by every member");
+    const Operand &u = p.spec.args[slot_arg(p, k, R.posU)];
+    if (u.kind == BES_TET_JACOBIAN) return fail("U cannot be a Jacobian operand");
+    if ((u.kind == BES_ELEMENTWISE) != (uo.kind == BES_ELEMENTWISE) || u.op != uo.op ||
+        u.alpha != uo.alpha || u.beta != uo.beta)
+      return fail("every member's U must be the same kind of function");
+    // per-lane offsets inside a 64-element tile are 32-bit
+    const int ua = slot_arg(p, k, R.posU);
+    for (int sidx = 0; sidx < u.nsrc; ++sidx) {
+      const int64_t se = stride_of(p, ua, R.posU, sidx, R.e);
+      const int64_t sj = stride_of(p, ua, R.posU, sidx, R.j);
+      const int64_t span = 64 * (se < 0 ? -se : se) + R.NJ * (sj < 0 ? -sj : sj);
+      if (span >= ((int64_t)1 << 31)) return fail("per-tile offsets exceed 32 bits");
+    }
+  }
+  for (int a : {s0, g0}) {
+    const Operand &o = p.spec.args[a];
+    if (o.kind != BES_ARRAY && o.kind != BES_VIEW) return fail("S and G must be arrays or views");
+  }
+  p.fem = R;
+  p.fem_ok = true;
+  p.fem_why.clear();
+}
+
+void analyse_fem(Plan &p) {
+  analyse_fem_grad(p);
+  if (p.fem_ok) return;
+  const std::string why_grad = p.fem_why;
+  analyse_fem_apply(p);
+  if (!p.fem_ok) p.fem_why = why_grad + "; " + p.fem_why;
+}
+
 // Merged stride of a group of canonical indices (in merge order) for one
 // operand; false if the group does not merge into one strided axis.
 bool merge_group(const Plan &p, int arg, int j, const std::vector<int> &grp,
@@ -307,6 +437,10 @@ bes_config default_config(const Plan &p) {
     c.template_id = BES_T_MFMA;
     c.p[0] = 128;
     c.p[1] = 128;
+  } else if (p.fem_ok && p.fem.cls == 1) {
+    c.template_id = BES_T_FEM_STREAM;
+    c.p[0] = 64;   // elements per tile
+    c.p[1] = 8;    // blocks of four waves per CU in the grid
   } else if (p.fem_ok) {
     c.template_id = BES_T_FEM_STREAM;
     c.p[0] = 64;   // elements per tile
@@ -448,7 +582,7 @@ void fill_src(const Plan &p, int arg, int j, const std::vector<int> &roles,
 
 int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a,
              std::string &err) {
-  if (!p.fem_ok) {
+  if (!p.fem_ok || p.fem.cls != 0) {
     err = "plan is not FEM-stream compatible: " + p.fem_why;
     return BES_E_UNSUPPORTED;
   }
@@ -550,6 +684,64 @@ int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a
         G.g_row = views ? (int32_t)(hi + 1) : 12;
         G.g_off = views ? 0 : f0.off0;
       }
+    }
+  }
+  return BES_OK;
+}
+
+int bind_fem_apply(const Plan &p, const void *const *src, void *const *out, FemApplyArgs &a,
+                   std::string &err) {
+  if (!p.fem_ok || p.fem.cls != 1) {
+    err = "plan is not of the FEM-stream apply class: " + p.fem_why;
+    return BES_E_UNSUPPORTED;
+  }
+  if (any_accumulate(p)) {
+    err = "the FEM-stream template overwrites its outputs";
+    return BES_E_UNSUPPORTED;
+  }
+  const FemRoles &R = p.fem;
+  const CanonEinsum &e = p.canon.form;
+  const int64_t item = p.spec.dtype == BES_FLOAT64 ? 8 : 4;
+  std::memset(&a, 0, sizeof a);
+  a.E = e.extent[R.e];
+  const int sa = slot_arg(p, 0, R.posS), ga = slot_arg(p, 0, R.posG);
+  a.S = (const char *)src[p.src_base[sa]] + p.spec.args[sa].src_offset[0] * item;
+  a.ss[0] = stride_of(p, sa, R.posS, 0, R.r);
+  a.ss[1] = stride_of(p, sa, R.posS, 0, R.i);
+  a.ss[2] = stride_of(p, sa, R.posS, 0, R.j);
+  a.G = (const char *)src[p.src_base[ga]] + p.spec.args[ga].src_offset[0] * item;
+  a.gs[0] = R.diag ? 0 : stride_of(p, ga, R.posG, 0, R.x);
+  a.gs[1] = stride_of(p, ga, R.posG, 0, R.r);
+  a.gs[2] = stride_of(p, ga, R.posG, 0, R.e);
+  a.n_members = e.b;
+  const Operand &u0 = p.spec.args[slot_arg(p, 0, R.posU)];
+  a.u_kind = u0.kind == BES_ELEMENTWISE ? FEM_SRC_ELEMENTWISE : FEM_SRC_ARRAY;
+  a.op = u0.op;
+  a.alpha = u0.alpha;
+  a.beta = u0.beta;
+  for (int k = 0; k < e.b; ++k) {
+    FemApplyMember &M = a.mem[k];
+    const int ua = slot_arg(p, k, R.posU);
+    const Operand &u = p.spec.args[ua];
+    M.u0 = src[p.src_base[ua]];
+    M.uoff0 = u.src_offset[0];
+    M.us0[0] = stride_of(p, ua, R.posU, 0, R.x);
+    M.us0[1] = stride_of(p, ua, R.posU, 0, R.e);
+    M.us0[2] = stride_of(p, ua, R.posU, 0, R.j);
+    if (u.kind == BES_ELEMENTWISE && u.nsrc > 1) {
+      M.u1 = src[p.src_base[ua] + 1];
+      M.uoff1 = u.src_offset[1];
+      M.us1[0] = stride_of(p, ua, R.posU, 1, R.x);
+      M.us1[1] = stride_of(p, ua, R.posU, 1, R.e);
+      M.us1[2] = stride_of(p, ua, R.posU, 1, R.j);
+    }
+    const int slot = p.slot_of_member[p.canon.member_map[k]];
+    const std::vector<int64_t> ost = out_strides(p, slot);
+    M.out = (char *)out[slot] +
+            (p.out_layout[slot].custom ? p.out_layout[slot].offset * item : 0);
+    for (size_t d = 0; d < e.out.size(); ++d) {
+      if (e.out[d] == R.e) M.oe = ost[d];
+      if (e.out[d] == R.i) M.oi = ost[d];
     }
   }
   return BES_OK;

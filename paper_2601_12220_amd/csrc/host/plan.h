@@ -15,7 +15,14 @@
 namespace bes {
 
 // FEM-stream roles, on the canonical form (see desc.h for the computation).
+// cls 0, the local-gradient class: T = S.U then out = G.T (desc.h FemArgs).
+// cls 1, the "apply" class (face mass, local divergence): W = G.U per
+// element, then out = S.W (desc.h FemApplyArgs); r is the index c that S and
+// G share, x the component index of U and G (the same index as c when
+// `diag`, the face-mass case).
 struct FemRoles {
+  int cls = 0;
+  bool diag = false;
   int e = -1, i = -1, j = -1, r = -1, x = -1;  // canonical index ordinals
   int NI = 1, NJ = 1, NR = 1, NX = 1;
   int posS = -1, posU = -1, posG = -1;         // canonical positions
@@ -114,6 +121,8 @@ bes_config default_config(const Plan &p);
 // remapping), `out` one pointer per slot.
 int bind_fem(const Plan &p, const void *const *src, void *const *out, FemArgs &a,
              std::string &err);
+int bind_fem_apply(const Plan &p, const void *const *src, void *const *out, FemApplyArgs &a,
+                   std::string &err);
 int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std::string &err);
 int bind_generic_ptrs(const Plan &p, const void *const *src, void *const *out, GenPtrs &ptrs);
 int bind_mfma(const Plan &p, const void *const *src, void *const *out, MfmaArgs &a,

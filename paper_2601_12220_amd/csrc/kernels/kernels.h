@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../desc.h"
+#include "../fem_shapes.h"
 
 namespace bes {
 
@@ -23,6 +24,13 @@ size_t fem_workspace_bytes(bool f64, int NI, int NJ, int NR);
 hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a, void *workspace,
                       int blocks_per_cu, int variant, hipStream_t stream,
                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+
+// FEM-stream "apply" class (face mass, local divergence): one launch over
+// (64-element tile, member) work items; a grid of at most `blocks_per_cu`
+// blocks of four waves per compute unit.  Events as for launch_fem.
+hipError_t launch_fem_apply(bool f64, int NI, int NJ, int NC, int NX, bool diag,
+                            const FemApplyArgs &a, int blocks_per_cu, hipStream_t stream,
+                            hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // Generic template: one launch over (slot, tile) pairs.  `dev` is the device
 // copy of `host`.

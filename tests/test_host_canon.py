@@ -508,3 +508,19 @@ def test_set_output_validates_slot():
         capi.bes_plan_set_output(p.h, 3)
     with pytest.raises(capi.BesError):
         capi.bes_plan_set_output(p.h, 0, -1)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_face_mass_and_divergence_plan_on_fem_stream(p):
+    # host-only: both DG-FEM classes at P1..P4 pick the FEM-stream template,
+    # and a reordered, renamed registration has the same key
+    ctx = Context()
+    for w in (workloads.face_mass(p=p, e=300, b=2), workloads.local_divergence(p=p, e=300, b=2)):
+        plan = ctx.register(w.notation, w.table, w.operands)
+        assert plan.template == "fem_stream", (w.name, plan.template)
+    w = workloads.face_mass(p=p, e=300, b=2)
+    k0 = ctx.register(w.notation, w.table, w.operands).key
+    # (F[f,e,j], M[i,f,j], J[f,e]) renamed f->q, e->z, j->m, i->n
+    rows = [[r[2], r[1], r[0]] for r in w.table]
+    k1 = ctx.register("qzm,nqm,qz->zn", rows, w.operands).key
+    assert k0 == k1

@@ -238,3 +238,56 @@ def test_functional_p4_batch_against_hand_materialized_numpy():
         u = np.sin(w.buffers[f"a{k}"].numpy()) + w.buffers[f"b{k}"].numpy()
         ref = np.einsum("rij,exr,ej->exi", D, J, u)
         np.testing.assert_allclose(got[k], ref, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# The face-mass and local-divergence classes (Section "Batched einsums in
+# DG-FEM Operators"; kernel patterns in Appendix "DG-FEM Batched Einsum Kernel
+# Patterns"): the oracle's loop nest on their notations against the listings'
+# semantics written per element with numpy matrix-vector products.
+# ---------------------------------------------------------------------------
+
+def test_face_mass_against_listing_semantics():
+    import workloads
+    w = workloads.face_mass(p=2, e=9, b=3)
+    vals = {k: v.numpy() for k, v in w.buffers.items()}
+    got = oracle.batched_einsum(w.notation, w.table, {a: vals[a] for a in w.operands})
+    J, M = vals["J"], vals["M"]
+    for k, row in enumerate(w.table):
+        F_ = vals[row[2]]
+        ref = np.zeros((9, M.shape[0]))
+        for e in range(9):
+            for f in range(4):                 # y[e] += J[f,e] * M[:,f,:] @ F[f,e,:]
+                ref[e] += J[f, e] * (M[:, f, :] @ F_[f, e, :])
+        np.testing.assert_allclose(got[k], ref, rtol=1e-13, atol=1e-13)
+
+
+def test_local_divergence_against_listing_semantics():
+    import workloads
+    w = workloads.local_divergence(p=1, e=7, b=2)
+    vals = {k: v.numpy() for k, v in w.buffers.items()}
+    got = oracle.batched_einsum(w.notation, w.table, {a: vals[a] for a in w.operands})
+    J, D = vals["J"], vals["D"]
+    for k, row in enumerate(w.table):
+        U = vals[row[2]]
+        ref = np.zeros((7, D.shape[1]))
+        for e in range(7):
+            for x in range(3):                 # component x of the vector field
+                for r in range(3):
+                    ref[e] += J[x, r, e] * (D[r] @ U[x, e, :])
+        np.testing.assert_allclose(got[k], ref, rtol=1e-13, atol=1e-13)
+
+
+def test_local_divergence_of_a_constant_field_is_zero():
+    # D with zero row sums differentiates constants to zero: with every
+    # component of the field constant in j, the divergence vanishes exactly
+    # up to rounding, for any geometry J
+    import workloads
+    w = workloads.local_divergence(p=1, e=5, b=1)
+    vals = {k: v.numpy().copy() for k, v in w.buffers.items()}
+    D = vals["D"]
+    D -= D.mean(axis=2, keepdims=True)        # rows sum to zero
+    U = np.broadcast_to(RNG.standard_normal((3, 5, 1)), (3, 5, 4)).copy()
+    vals["U0"] = U
+    got = oracle.batched_einsum(w.notation, w.table, vals)
+    assert np.abs(got[0]).max() < 1e-13

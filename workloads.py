@@ -150,6 +150,50 @@ def config3(e: int = 1 << 19, ni: int = 35, dtype: str = "float64") -> Workload:
 
 
 # ---------------------------------------------------------------------------
+# The other two DG-FEM classes at the paper's shapes (P1..P4, e = 10^5, a
+# sweep over b), as their kernel-pattern listings index the arrays:
+#   face mass        y_k[e,i] = sum_{f,j} J[f,e] M[i,f,j] F_k[f,e,j]
+#                    'fe,ifj,fej->ei'; f = 4 faces, j = face DOFs
+#   local divergence y_k[e,i] = sum_{x,r,j} J[x,r,e] D[r,i,j] U_k[x,e,j]
+#                    'xre,rij,xej->ei'; U_k holds the three components of a
+#                    vector field as planes U_k[x] of one buffer
+# ---------------------------------------------------------------------------
+
+VOLUME_DOFS = {1: 4, 2: 10, 3: 20, 4: 35}     # P_k tetrahedron
+FACE_DOFS = {1: 3, 2: 6, 3: 10, 4: 15}        # P_k triangle
+
+
+def face_mass(p: int = 3, e: int = 100_000, b: int = 1, dtype: str = "float64") -> Workload:
+    ni, nj = VOLUME_DOFS[p], FACE_DOFS[p]
+    bufs = {"J": _uniform(6, 0, (4, e), 0.5, 1.5, dtype),
+            "M": _uniform(6, 1, (ni, 4, nj), -1.0, 1.0, dtype)}
+    ops = {"J": _dense("J", bufs["J"], dtype), "M": _dense("M", bufs["M"], dtype)}
+    table = []
+    for k in range(b):
+        bufs[f"F{k}"] = _normal(6, 2 + k, (4, e, nj), dtype)
+        ops[f"F{k}"] = _dense(f"F{k}", bufs[f"F{k}"], dtype)
+        table.append(["J", "M", f"F{k}"])
+    return Workload(f"face_mass_p{p}", "fe,ifj,fej->ei", table, ops, bufs, dtype,
+                    {"e": e, "ni": ni, "nj": nj, "p": p})
+
+
+def local_divergence(p: int = 3, e: int = 100_000, b: int = 1,
+                     dtype: str = "float64") -> Workload:
+    n = VOLUME_DOFS[p]
+    jac = fem_jacobian(7, 0, e, "float64")             # [e, x, r]
+    bufs = {"J": jac.permute(1, 2, 0).contiguous().to(_tdtype(dtype)),   # [x, r, e]
+            "D": _uniform(7, 1, (3, n, n), -1.0, 1.0, dtype)}
+    ops = {"J": _dense("J", bufs["J"], dtype), "D": _dense("D", bufs["D"], dtype)}
+    table = []
+    for k in range(b):
+        bufs[f"U{k}"] = _normal(7, 2 + k, (3, e, n), dtype)
+        ops[f"U{k}"] = _dense(f"U{k}", bufs[f"U{k}"], dtype)
+        table.append(["J", "D", f"U{k}"])
+    return Workload(f"local_div_p{p}", "xre,rij,xej->ei", table, ops, bufs, dtype,
+                    {"e": e, "ni": n, "nj": n, "p": p})
+
+
+# ---------------------------------------------------------------------------
 # Config 5: dense pair sharing T: 'abij,cdab->cdij' rows (T, V), (T, W')
 # with W'[c,d,a,b] = W[a,b,c,d] a permuted view.
 # ---------------------------------------------------------------------------
