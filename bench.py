@@ -79,6 +79,8 @@ def algorithmic_bytes(w):
 
 def fem_flops(w):
     """FLOPs of the factored evaluation the FEM-stream kernels perform."""
+    if "e" not in w.info:
+        return None
     e, ni = w.info["e"], w.info["ni"]
     if w.name.startswith("fem_grad_p3"):
         return e * (2 * 3 * ni * ni + 3 * 2 * 3 * ni)          # T once, 3 members
@@ -306,6 +308,70 @@ def _nt(w):
     return w.notation, w.table, w.operands
 
 
+def run_tccg(min_s, copy_gbs, cases=24):
+    """Binary contractions with affine operands (alpha_1 A + beta_1)(alpha_2 B +
+    beta_2) in FP64, the TCCG extension of the paper, on the seeded stand-in
+    generator (the suite itself is not available).  FLOP throughput counts the
+    contraction (2 x product of all extents) plus the affine maps (2 per
+    operand element); roofline = min(FP64 peak, FLOPs / footprint bytes x HBM
+    peak) with footprint = A + B + C."""
+    import workloads
+    rows = {}
+    fracs = []
+    mem_bound = 0
+    for c in range(cases):
+        w = workloads.tccg_like(c)
+        log(f"[bench] tccg_like {c}: {w.notation}")
+        r = run_fem(w, min_s, tune_first=False)
+        ext = w.info["ext"]
+        space = 1
+        for v in ext.values():
+            space *= v
+        na, nb = w.buffers["A"].numel(), w.buffers["B"].numel()
+        nc = 1
+        for s_ in w.out_shape():
+            nc *= s_
+        flops = 2 * space + 2 * (na + nb)
+        foot = 8 * (na + nb + nc)
+        roof = min(FP64_PEAK_TFLOPS * 1e12, flops / foot * HBM_PEAK_GBS * 1e9)
+        got = flops / (r["ms"] * 1e-3)
+        bound = "hbm" if roof < FP64_PEAK_TFLOPS * 1e12 else "fp64"
+        mem_bound += bound == "hbm"
+        fracs.append(got / roof)
+        rows[w.notation] = {"GFLOP/s": round(got / 1e9, 1),
+                            "roofline_GFLOP/s": round(roof / 1e9, 1),
+                            "frac_roofline": round(got / roof, 4), "bound": bound,
+                            "GB/s": round(r["gbs"], 1), "ms": round(r["ms"], 5),
+                            "template": r["template"], "buffer_sets": r["buffer_sets"]}
+    geo = math.exp(sum(math.log(max(f, 1e-9)) for f in fracs) / len(fracs))
+    return {"workload": f"{cases} seeded TCCG-like FP64 binary contractions with affine "
+                        "operands (stand-in for the TCCG suite)",
+            "geomean_frac_roofline": round(geo, 4), "memory_bound_cases": mem_bound,
+            "cases": rows}
+
+
+def run_canonicalization():
+    """Host time to canonicalize one batched einsum (registration: parse,
+    induced graph, canonical labeling, reconstruction, key, lookup), as in
+    Section "Time to canonicalize a batched einsum" (paper: < 1 ms for every
+    TCCG einsum on a laptop CPU): every einsum of the TCCG-like stand-in
+    suite and of the 256-einsum uneven batch, and the FEM workloads."""
+    import workloads
+    from paper_2601_12220_amd import Context
+    ctx = Context()
+    suites = {"tccg_like_24": [workloads.tccg_like(c) for c in range(24)],
+              "uneven_batch_256": workloads.config4(),
+              "fem": [workloads.config1(), workloads.config2(e=1 << 10),
+                      workloads.config3(e=1 << 10), workloads.face_mass(p=4, e=1 << 10, b=8),
+                      workloads.local_divergence(p=4, e=1 << 10, b=8), workloads.config5(a=8, i=8)]}
+    out = {}
+    for name, ws in suites.items():
+        t = [register_us(ctx, w, reps=10) for w in ws]
+        out[name] = {"einsums": len(ws), "mean_us": round(statistics.fmean(t), 1),
+                     "max_us": round(max(t), 1), "under_1ms": sum(x < 1000 for x in t)}
+    return out
+
+
 def run_tiny(min_s):
     """Config 1: 'ij,ej->ei', b = 3, e = 64, FP64 -- launch latency, parity
     and the keys of 8 random renamings / permutations."""
@@ -501,8 +567,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 20)
     ap.add_argument("--only", default="",
-                    help="comma list of extra workloads: f32,p4,apply,tiny,batch,dense "
-                         "(default: all)")
+                    help="comma list of extra workloads: f32,p4,apply,tccg,canon,tiny,batch,"
+                         "dense (default: all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -525,7 +591,7 @@ def main():
     import workloads
     assert torch.cuda.is_available(), "needs a HIP device"
     only = (set(args.only.split(",")) if args.only
-            else {"f32", "p4", "apply", "tiny", "batch", "dense"})
+            else {"f32", "p4", "apply", "tccg", "canon", "tiny", "batch", "dense"})
     min_s = args.min_time
 
     log("[bench] copy bandwidth (1 GiB device-to-device)")
@@ -543,6 +609,11 @@ def main():
         extra["fem_grad_functional_p4_f64"] = fem_line(r, copy_gbs, FP64_PEAK_TFLOPS)
     if "apply" in only:
         extra.update(run_apply_sweep(args.sweep_min_time, copy_gbs))
+    if "tccg" in only:
+        extra["tccg_affine_f64"] = run_tccg(args.sweep_min_time, copy_gbs)
+    if "canon" in only:
+        log("[bench] canonicalization time per batched einsum (host)")
+        extra["canonicalization_us"] = run_canonicalization()
     if "tiny" in only:
         log("[bench] tiny batch 'ij,ej->ei' b=3 e=64 FP64")
         extra["fem_matvec_tiny"] = run_tiny(min_s)

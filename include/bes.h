@@ -67,10 +67,14 @@ enum bes_kind {
   BES_VIEW = 1,         /* M(A)[idx] = S0[src_offset[0] + sum idx_k*stride_k] */
   BES_ELEMENTWISE = 2,  /* M(A)[idx] = alpha*op(S0[idx]) + beta (+ S1[idx]
                            when nsrc == 2) */
-  BES_TET_JACOBIAN = 3  /* M(A)[e,x,r] = S0[e,r+1,x] - S0[e,0,x]: Jacobian of
+  BES_TET_JACOBIAN = 3, /* M(A)[e,x,r] = S0[e,r+1,x] - S0[e,0,x]: Jacobian of
                            the affine map of a tetrahedron whose 4 vertex
                            coordinates are S0[e,4,3]; the operand is 3-d with
                            extents (e,3,3); src_strides[0] are S0's strides */
+  BES_EXPR = 4          /* M(A)[idx] = f(S0[idx], S1[idx]) for an expression
+                           body f given at registration (bes_register_expr):
+                           the substitution-rule bodies of the paper's
+                           retrieval listing; compiled at run time */
 };
 
 enum bes_unary { BES_OP_ID = 0, BES_OP_SIN = 1, BES_OP_COS = 2, BES_OP_SQUARE = 3 };
@@ -117,8 +121,16 @@ enum bes_template {
                             p[1] = lanes per output (1,2,4,...,64),
                             p[2] = chunks of the shared contracted index
                             space per output (0 or 1: none; up to 64) */
-  BES_T_MFMA = 3         /* dense contraction on MFMA (FP32 in, FP32 acc);
+  BES_T_MFMA = 3,        /* dense contraction on MFMA (FP32 in, FP32 acc);
                             p[0] = tile M, p[1] = tile N, p[2] = split */
+  BES_T_GETT = 4         /* any binary contraction (FP32 or FP64) on the
+                            matrix cores: arbitrary index groups and strides
+                            through offset tables, affine operands
+                            alpha*A+beta applied while loading, ragged
+                            edges; p[0] = tile M, p[1] = tile N (64),
+                            p[2] = K ranges per output tile (0: chosen by
+                            the launcher; > 1: partial tiles add
+                            atomically into the zeroed output) */
 };
 
 typedef struct bes_config {
@@ -153,6 +165,22 @@ int bes_register(bes_ctx *ctx, const char *notation, int32_t b, int32_t n,
                  bes_plan **out);
 void bes_plan_destroy(bes_plan *plan);
 
+/* bes_register with expression operands (kind BES_EXPR; Definition
+ * "Functional Batched Einstein Summation" with the substitution-rule bodies
+ * of Section "Integration ...", e.g. "s0*s0", "3*cos(s0)+5", "sin(s0)+s1").
+ * exprs[a] is the body of argument a (NULL for other kinds; exprs may be NULL
+ * when no argument is an expression).  A body is a C expression over s0 and
+ * s1 (the argument's first and second source at the same index, each through
+ * its own offset and strides; nsrc 1 or 2), decimal constants, + - * / and
+ * parentheses, and the functions sin cos tan exp log sqrt fabs tanh pow fmin
+ * fmax; anything else is BES_E_INVALID.  Bodies are not part of the
+ * canonical key (a tuning record transfers between functional variants).
+ * Plans with expression operands are evaluated by the generic template,
+ * built with hipRTC for their bodies at the first launch on a device. */
+int bes_register_expr(bes_ctx *ctx, const char *notation, int32_t b, int32_t n,
+                      int32_t n_args, const bes_operand *args, const int32_t *table,
+                      const char *const *exprs, bes_plan **out);
+
 /* Canonical key (the tuning-database identity): the canonical batched einsum
  * with its extents and dtypes, identical for every isomorphic registration
  * (Definition "Canonicalization of a batched einsum").  Written with a NUL
@@ -174,6 +202,22 @@ int bes_plan_canonical(const bes_plan *plan, char *buf, size_t cap, size_t *len)
  * Any pointer may be NULL.  *n_index (optional) gets the number of indices. */
 int bes_plan_maps(const bes_plan *plan, int32_t *member_map, int32_t *pos_map,
                   int32_t *arg_map, char *index_map, int32_t *n_index);
+
+/* Identify one registered batched einsum as another (Algorithm
+ * "IdentifyAsEinsum"): when `raised` (for example one raised from a traced
+ * program) and `ref` (the batched einsum a transformation or tuning record
+ * was written for) have the same canonical form, return the composed
+ * substitution from the reference's names to the raised one's:
+ *   member_map[i] = raised member of reference member i       (b entries)
+ *   pos_map[j]    = raised operand position of reference pos j (n entries)
+ *   arg_map[a]    = raised argument id of reference argument a (n_args)
+ *   index_map[x]  = raised letter of reference index 'a' + x   (indexed by
+ *                   the reference's index letter minus 'a'; 26 entries,
+ *                   untouched where the reference has no such index)
+ * Any pointer may be NULL.  BES_E_INVALID when the canonical forms differ
+ * (the algorithm's exception).  Host only. */
+int bes_identify(const bes_plan *ref, const bes_plan *raised, int32_t *member_map,
+                 int32_t *pos_map, int32_t *arg_map, char *index_map);
 
 /* Induced graph of the registration (Appendix B.1) and of the canonical form:
  * n_nodes, then optionally the row-major adjacency (n_nodes^2 bytes, 0/1) and

@@ -72,3 +72,49 @@ def tet_jacobian(V) -> np.ndarray:
         for r in range(3):
             J[:, x, r] = V[:, r + 1, x] - V[:, 0, x]
     return J
+
+
+# Functions an expression body may call, each as numpy evaluates it in FP64.
+_EXPR_FUNCS = {"sin": np.sin, "cos": np.cos, "tan": np.tan, "exp": np.exp, "log": np.log,
+               "sqrt": np.sqrt, "fabs": np.fabs, "tanh": np.tanh, "pow": np.power,
+               "fmin": np.fmin, "fmax": np.fmax}
+
+
+def expression(body: str, src0, src1=None) -> np.ndarray:
+    """M(A)[idx] = body(S0[idx], S1[idx]): a substitution-rule body of the
+    functional retrieval listing (e.g. "s0*s0", "3*cos(s0)+5", "sin(s0)"),
+    evaluated in FP64 over the whole domain.  The body is read with Python's
+    own parser and only numbers, s0, s1, + - * / , unary signs and the
+    functions above are evaluated."""
+    import ast
+
+    env = {"s0": np.asarray(src0, dtype=np.float64)}
+    env["s1"] = np.asarray(src1, dtype=np.float64) if src1 is not None else env["s0"]
+
+    def ev(node):
+        if isinstance(node, ast.Expression):
+            return ev(node.body)
+        if isinstance(node, ast.Constant) and isinstance(node.value, (int, float)):
+            return float(node.value)
+        if isinstance(node, ast.Name) and node.id in ("s0", "s1"):
+            return env[node.id]
+        if isinstance(node, ast.UnaryOp) and isinstance(node.op, (ast.USub, ast.UAdd)):
+            v = ev(node.operand)
+            return -v if isinstance(node.op, ast.USub) else v
+        if isinstance(node, ast.BinOp):
+            a, b = ev(node.left), ev(node.right)
+            if isinstance(node.op, ast.Add):
+                return a + b
+            if isinstance(node.op, ast.Sub):
+                return a - b
+            if isinstance(node.op, ast.Mult):
+                return a * b
+            if isinstance(node.op, ast.Div):
+                return a / b
+        if (isinstance(node, ast.Call) and isinstance(node.func, ast.Name) and
+                node.func.id in _EXPR_FUNCS and not node.keywords):
+            return _EXPR_FUNCS[node.func.id](*[ev(a) for a in node.args])
+        raise ValueError(f"not an expression body: {ast.dump(node)}")
+
+    val = ev(ast.parse(body, mode="eval"))
+    return np.broadcast_to(np.asarray(val, dtype=np.float64), env["s0"].shape).copy()

@@ -27,7 +27,7 @@ def make_operand(shape, dtype="float64", kind="array", sources=None, offset=0,
     o = capi.bes_operand()
     o.kind = {"array": capi.BES_ARRAY, "view": capi.BES_VIEW,
               "elementwise": capi.BES_ELEMENTWISE,
-              "tet_jacobian": capi.BES_TET_JACOBIAN}[kind]
+              "tet_jacobian": capi.BES_TET_JACOBIAN, "expr": capi.BES_EXPR}[kind]
     o.dtype = capi.DTYPE_CODE[dtype]
     o.ndim = len(shape)
     for d, s in enumerate(shape):
@@ -46,17 +46,23 @@ def make_operand(shape, dtype="float64", kind="array", sources=None, offset=0,
     if src_offsets:
         for k, off in enumerate(src_offsets):
             o.src_offset[k] = int(off)
-    o.op = capi.OP_CODE[op]
+    o.op = capi.OP_CODE.get(op, 0)
     o.alpha = float(alpha)
     o.beta = float(beta)
     return o
 
 
 def _operand_from_desc(d) -> capi.bes_operand:
-    """From a duck-typed descriptor with name/shape/dtype/kind/sources/... ."""
-    return make_operand(d.shape, d.dtype, d.kind, d.sources, getattr(d, "offset", 0),
-                        getattr(d, "strides", None), getattr(d, "op", "id"),
-                        getattr(d, "alpha", 1.0), getattr(d, "beta", 0.0))
+    """From a duck-typed descriptor with name/shape/dtype/kind/sources/... .
+    An element-wise operand with ``strides`` reads its first source through
+    that view (offset and strides)."""
+    strides = getattr(d, "strides", None)
+    offset = getattr(d, "offset", 0)
+    ew_view = d.kind in ("elementwise", "expr") and strides is not None
+    return make_operand(d.shape, d.dtype, d.kind, d.sources, offset, strides,
+                        getattr(d, "op", "id"), getattr(d, "alpha", 1.0), getattr(d, "beta", 0.0),
+                        src_strides=[strides] if ew_view else None,
+                        src_offsets=[offset] if ew_view else None)
 
 
 def _stream_handle(stream=None) -> int:
@@ -91,17 +97,20 @@ class Context:
         bes_operand instances paired with a ``sources`` list)."""
         names = arg_order or sorted({a for row in table for a in row})
         idx = {nm: k for k, nm in enumerate(names)}
-        descs, sources = [], []
+        descs, sources, exprs = [], [], []
         for nm in names:
             d = operands[nm]
             if isinstance(d, tuple):
                 descs.append(d[0])
                 sources.append(list(d[1]))
+                exprs.append(d[2] if len(d) > 2 else None)
             else:
                 descs.append(_operand_from_desc(d))
                 sources.append(list(d.sources) if d.sources else [nm])
+                exprs.append(getattr(d, "expr", None) if d.kind == "expr" else None)
         flat = [idx[a] for row in table for a in row]
-        h, status = capi.bes_register(self.h, notation, len(table), len(table[0]), descs, flat)
+        h, status = capi.bes_register(self.h, notation, len(table), len(table[0]), descs, flat,
+                                      exprs)
         return Plan(self, h, notation, [list(r) for r in table], names, sources, status)
 
     def record(self, key: str, cfg: capi.bes_config, seconds: float, arch: str = "gfx950"):

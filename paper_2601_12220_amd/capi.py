@@ -29,12 +29,12 @@ DTYPE_CODE = {"int8": 1, "int32": 2, "int64": 3, "float16": 4, "float32": 5,
               "float64": 6, "complex64": 7, "complex128": 8}
 
 # operand kinds and unary ops
-BES_ARRAY, BES_VIEW, BES_ELEMENTWISE, BES_TET_JACOBIAN = 0, 1, 2, 3
+BES_ARRAY, BES_VIEW, BES_ELEMENTWISE, BES_TET_JACOBIAN, BES_EXPR = 0, 1, 2, 3, 4
 OP_CODE = {"id": 0, "sin": 1, "cos": 2, "square": 3}
 
 # templates
 BES_T_AUTO, BES_T_FEM_STREAM, BES_T_GENERIC, BES_T_MFMA = 0, 1, 2, 3
-TEMPLATE_NAME = {0: "auto", 1: "fem_stream", 2: "generic", 3: "mfma"}
+TEMPLATE_NAME = {0: "auto", 1: "fem_stream", 2: "generic", 3: "mfma", 4: "gett"}
 
 BES_MAX_DIM = 8
 BES_MAX_SRC = 2
@@ -111,6 +111,9 @@ def load():
         "bes_plan_set_output": ([P, i32, ctypes.c_int64, i64p, i32], i32),
         "bes_fill_zero": ([P, ctypes.c_int64, i32, P], i32),
         "bes_launch_noalloc": ([P, PP, PP, P], i32),
+        "bes_identify": ([P, P, i32p, i32p, i32p, ctypes.c_char_p], i32),
+        "bes_register_expr": ([P, cp, i32, i32, i32, ctypes.POINTER(bes_operand), i32p,
+                               ctypes.POINTER(ctypes.c_char_p), PP], i32),
         "bes_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -152,13 +155,22 @@ def bes_ctx_destroy(h):
     load().bes_ctx_destroy(h)
 
 
-def bes_register(ctx, notation: str, b: int, n: int, args, table):
-    """args: list of bes_operand; table: flat b*n ints.  Returns (plan, status)."""
+def bes_register(ctx, notation: str, b: int, n: int, args, table, exprs=None):
+    """args: list of bes_operand; table: flat b*n ints; exprs: per argument the
+    body of an expression operand or None.  Returns (plan, status)."""
     arr = (bes_operand * len(args))(*args)
     tab = (ctypes.c_int32 * len(table))(*table)
     h = ctypes.c_void_p()
-    rc = load().bes_register(ctx, notation.encode(), b, n, len(args), arr, tab, ctypes.byref(h))
-    check(rc, "bes_register")
+    if exprs is not None and any(x is not None for x in exprs):
+        bodies = (ctypes.c_char_p * len(args))(*[x.encode() if x is not None else None
+                                                   for x in exprs])
+        rc = load().bes_register_expr(ctx, notation.encode(), b, n, len(args), arr, tab,
+                                      bodies, ctypes.byref(h))
+        check(rc, "bes_register_expr")
+    else:
+        rc = load().bes_register(ctx, notation.encode(), b, n, len(args), arr, tab,
+                                 ctypes.byref(h))
+        check(rc, "bes_register")
     return h, rc
 
 
@@ -308,3 +320,16 @@ def bes_plan_set_output(h, slot: int, offset: int = 0, strides=None, accumulate:
 def bes_fill_zero(ptr: int, n: int, dtype: int, stream: int = 0) -> None:
     check(load().bes_fill_zero(ctypes.c_void_p(ptr), int(n), dtype, ctypes.c_void_p(stream)),
           "bes_fill_zero")
+
+
+def bes_identify(ref, raised, b: int, n: int, n_args: int):
+    """(member_map, pos_map, arg_map, index_map) from the reference plan's names
+    to the raised plan's (index_map: dict reference letter -> raised letter)."""
+    mm = (ctypes.c_int32 * max(1, b))()
+    pm = (ctypes.c_int32 * max(1, n))()
+    am = (ctypes.c_int32 * max(1, n_args))()
+    im = ctypes.create_string_buffer(b"\0" * 27, 27)
+    check(load().bes_identify(ref, raised, mm, pm, am, im), "bes_identify")
+    raw = im.raw[:26]
+    imap = {chr(ord("a") + x): chr(raw[x]) for x in range(26) if raw[x] != 0}
+    return list(mm)[:b], list(pm)[:n], list(am)[:n_args], imap

@@ -19,6 +19,7 @@
 #include "host/graph.h"
 #include "host/plan.h"
 #include "host/spec.h"
+#include "jit.h"
 #include "kernels/kernels.h"
 
 struct bes_ctx {
@@ -133,7 +134,44 @@ int generic_descriptor(const bes::Plan &p, const bes_config &cfg, hipStream_t st
   return BES_OK;
 }
 
+// The plan's GETT offset tables for its current output layouts on the
+// current device: built on the host and uploaded once (the first launch of
+// a layout allocates and copies synchronously; later launches reuse them).
+int gett_tables(const bes::Plan &p, const bes::Plan::GettCopy **out, std::string &err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return BES_E_HIP;
+  }
+  for (const auto &c : p.gett_cache)
+    if (c.device == dev && bes::same_layouts(c.layouts, p.out_layout)) {
+      *out = &c;
+      return BES_OK;
+    }
+  bes::Plan::GettCopy c;
+  c.layouts = p.out_layout;
+  c.device = dev;
+  std::vector<int64_t> tab;
+  int rc = bes::bind_gett_static(p, tab, c.args, err);
+  if (rc) return rc;
+  const size_t bytes = std::max<size_t>(tab.size(), 1) * sizeof(int64_t);
+  if ((e = hipMalloc((void **)&c.dev, bytes)) != hipSuccess ||
+      (e = hipMemcpy(c.dev, tab.data(), tab.size() * sizeof(int64_t), hipMemcpyHostToDevice)) !=
+          hipSuccess) {
+    if (c.dev) (void)hipFree(c.dev);
+    err = std::string("GETT table upload: ") + hipGetErrorString(e);
+    return BES_E_HIP;
+  }
+  p.gett_cache.push_back(c);
+  *out = &p.gett_cache.back();
+  return BES_OK;
+}
+
 void free_gen_cache(const bes::Plan &p) {
+  for (auto &c : p.gett_cache)
+    if (c.dev) (void)hipFree(c.dev);
+  p.gett_cache.clear();
   for (auto &c : p.gen_cache) {
     if (c.dev) (void)hipFree(c.dev);
     if (c.host) (void)hipHostFree(c.host);
@@ -222,12 +260,18 @@ void bes_ctx_destroy(bes_ctx *ctx) { delete ctx; }
 
 int bes_register(bes_ctx *ctx, const char *notation, int32_t b, int32_t n, int32_t n_args,
                  const bes_operand *args, const int32_t *table, bes_plan **out) {
+  return bes_register_expr(ctx, notation, b, n, n_args, args, table, nullptr, out);
+}
+
+int bes_register_expr(bes_ctx *ctx, const char *notation, int32_t b, int32_t n,
+                      int32_t n_args, const bes_operand *args, const int32_t *table,
+                      const char *const *exprs, bes_plan **out) {
   if (!out) return fail(BES_E_INVALID, "out is NULL");
   *out = nullptr;
   try {
     bes_plan *P = new bes_plan;
     std::string err;
-    int rc = bes::make_spec(notation, b, n, n_args, args, table, P->p.spec, err);
+    int rc = bes::make_spec(notation, b, n, n_args, args, table, P->p.spec, err, exprs);
     if (rc == BES_OK) rc = bes::build_plan(P->p, err);
     if (rc != BES_OK) {
       delete P;
@@ -391,8 +435,12 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
     if (rc) return fail(rc, err);
     GenPtrs ptrs;
     bes::bind_generic_ptrs(p, src.data(), out_ptrs, ptrs);
+    hipFunction_t jk = nullptr, jz = nullptr;
+    if (!p.exprs.empty() && (rc = bes::jit_generic(f64, p.exprs, &jk, &jz, err)) != BES_OK)
+      return fail(rc, err);
     if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
-    e = bes::launch_generic(f64, gd->dev, *gd->host, ptrs, stream);
+    e = p.exprs.empty() ? bes::launch_generic(f64, gd->dev, *gd->host, ptrs, stream)
+                        : bes::launch_generic_jit(jk, jz, gd->dev, *gd->host, ptrs, stream);
     if (e != hipSuccess) return hip_fail(e, "generic launch");
     if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
     return BES_OK;
@@ -445,6 +493,21 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
       if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
       e = bes::launch_mfma(a, p.cfg.p[0], p.cfg.p[1], stream);
       if (e != hipSuccess) return hip_fail(e, "MFMA launch");
+      if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
+      return BES_OK;
+    }
+    case BES_T_GETT: {
+      // overlapping accumulating outputs need the generic template's atomics
+      if (accumulating_slots_overlap(p, out_ptrs)) return run_generic(p.cfg);
+      const bes::Plan::GettCopy *gc = nullptr;
+      int rc = gett_tables(p, &gc, err);
+      if (rc) return fail(rc, err);
+      GettArgs a = gc->args;
+      a.tab = gc->dev;
+      bes::bind_gett_ptrs(p, src.data(), out_ptrs, a);
+      if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
+      e = bes::launch_gett(f64, a, p.cfg.p[2], stream);
+      if (e != hipSuccess) return hip_fail(e, "GETT launch");
       if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
       return BES_OK;
     }
@@ -579,6 +642,10 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
       return fail(BES_E_INVALID, "NULL plan");
     }
     const bes::Plan &p = plans[k]->p;
+    if (!p.exprs.empty()) {
+      bes_batch_destroy(B);
+      return fail(BES_E_UNSUPPORTED, "plans with expression operands launch with bes_launch");
+    }
     bool f64 = p.spec.dtype == BES_FLOAT64;
     if (k == 0) B->f64 = f64;
     if (f64 != B->f64) {
@@ -717,6 +784,27 @@ int bes_batch_launch(bes_batch *B, const void *const *const *src_ptrs, void *con
   e = bes::launch_persistent(B->f64, B->d_table, B->d_ptrs, B->d_items, B->n_items, B->d_counters,
                              B->grid, stream, (int)B->plans.size(), B->any_split);
   if (e != hipSuccess) return hip_fail(e, "persistent launch");
+  return BES_OK;
+}
+
+int bes_identify(const bes_plan *ref, const bes_plan *raised, int32_t *member_map,
+                 int32_t *pos_map, int32_t *arg_map, char *index_map) {
+  if (!ref || !raised) return fail(BES_E_INVALID, "NULL plan");
+  const bes::Plan &r = ref->p, &k = raised->p;
+  if (r.key != k.key)
+    return fail(BES_E_INVALID, "the batched einsums are not isomorphic: canonical forms differ");
+  const bes::Canonical &cr = r.canon, &ck = k.canon;
+  // canonical name -> reference name and canonical name -> raised name,
+  // composed: reference name -> raised name
+  if (member_map)
+    for (size_t c = 0; c < cr.member_map.size(); ++c) member_map[cr.member_map[c]] = ck.member_map[c];
+  if (pos_map)
+    for (size_t c = 0; c < cr.pos_map.size(); ++c) pos_map[cr.pos_map[c]] = ck.pos_map[c];
+  if (arg_map)
+    for (size_t c = 0; c < cr.arg_map.size(); ++c) arg_map[cr.arg_map[c]] = ck.arg_map[c];
+  if (index_map)
+    for (size_t c = 0; c < cr.index_map.size(); ++c)
+      index_map[cr.index_map[c]] = (char)('a' + ck.index_map[c]);
   return BES_OK;
 }
 

@@ -117,8 +117,9 @@ typedef struct FemApplyArgs {
 #define BES_GEN_MAX_B 16
 
 // GEN_ELEMENTWISE reads one source, GEN_ELEMENTWISE2 adds a second source;
-// GEN_TET is S0[pos0] - S0[pos1] (both positions in the first source).
-enum { GEN_ARRAY = 0, GEN_ELEMENTWISE = 1, GEN_TET = 2, GEN_ELEMENTWISE2 = 3 };
+// GEN_TET is S0[pos0] - S0[pos1] (both positions in the first source);
+// GEN_EXPR is expression body `op` of the plan at (S0[pos0], S1[pos1]).
+enum { GEN_ARRAY = 0, GEN_ELEMENTWISE = 1, GEN_TET = 2, GEN_ELEMENTWISE2 = 3, GEN_EXPR = 4 };
 
 typedef struct GenLayout {
   int32_t kind, op;
@@ -209,3 +210,43 @@ typedef struct MfmaArgs {
   MfmaMember mem[BES_MFMA_MAX_B];
   MfmaSlot slot[BES_MFMA_MAX_B];
 } MfmaArgs;
+
+// ---------------------------------------------------------------------------
+// GETT template: a general binary contraction on the matrix cores,
+//   C_s[M, N] (+)= sum over members m of slot s of
+//                  sum_K (alpha_A A_m[M, K] + beta_A) (alpha_B B_m[K, N] + beta_B)
+// where M, N and K are arbitrary groups of indices with arbitrary strides:
+// operand addresses come from offset tables, row and column offsets added
+// (address of A[m, k] = rowA[m] + colA[k]).  The affine operands are the
+// linear polynomials of arrays of Section "TCCG Benchmark suite with
+// Unmaterialized Operands".
+// ---------------------------------------------------------------------------
+#define BES_GETT_MAX_B 8
+
+typedef struct GettMember {
+  const void *A;
+  const void *B;
+  int64_t rowA, colA, rowB, colB;   // table offsets (int64 entries) in `tab`
+  double a_alpha, a_beta, b_alpha, b_beta;
+  int32_t a_kfast;                  // A's tile is read along K (else along M)
+  int32_t b_nfast;                  // B's tile is read along N (else along K)
+} GettMember;
+
+typedef struct GettSlot {
+  void *C;
+  int64_t rowC, colC;               // table offsets in `tab`
+  int32_t m0, m1;                   // members [m0, m1) are summed into C
+  int32_t acc;                      // add into C instead of overwriting it
+  int32_t pad;
+} GettSlot;
+
+typedef struct GettArgs {
+  int64_t M, N, K;
+  const int64_t *tab;               // device offset tables
+  int32_t n_members, n_slots;
+  int32_t ksplit;                   // K ranges per output tile (> 1: partial
+                                    // tiles add atomically into C)
+  int32_t pad;
+  GettMember mem[BES_GETT_MAX_B];
+  GettSlot slot[BES_GETT_MAX_B];
+} GettArgs;

@@ -173,8 +173,10 @@ void analyse_fem_grad(Plan &p) {
     if (s.kind != BES_ARRAY && s.kind != BES_VIEW) return fail("S must be an array or view");
     const Operand &u = p.spec.args[slot_arg(p, k, R.posU)];
     if (u.kind == BES_TET_JACOBIAN) return fail("U cannot be a Jacobian operand");
+    if (u.kind == BES_EXPR) return fail("expression operands run on the generic template");
     if (R.posG >= 0) {
       const Operand &g = p.spec.args[slot_arg(p, k, R.posG)];
+      if (g.kind == BES_EXPR) return fail("expression operands run on the generic template");
       if (g.kind == BES_TET_JACOBIAN && (R.NX != 3 || R.NR != 3))
         return fail("Jacobian operand needs x = r = 3");
     }
@@ -299,6 +301,7 @@ void analyse_fem_apply(Plan &p) {
       return fail("S and G must be shared by every member");
     const Operand &u = p.spec.args[slot_arg(p, k, R.posU)];
     if (u.kind == BES_TET_JACOBIAN) return fail("U cannot be a Jacobian operand");
+    if (u.kind == BES_EXPR) return fail("expression operands run on the generic template");
     if ((u.kind == BES_ELEMENTWISE) != (uo.kind == BES_ELEMENTWISE) || u.op != uo.op ||
         u.alpha != uo.alpha || u.beta != uo.beta)
       return fail("every member's U must be the same kind of function");
@@ -416,12 +419,200 @@ void analyse_mfma(Plan &p) {
   p.mfma_why.clear();
 }
 
+// Any pure binary contraction (every index in exactly two of A, B and the
+// output) with array, view or affine (alpha*S0 + beta) operands.
+void analyse_gett(Plan &p) {
+  const CanonEinsum &e = p.canon.form;
+  auto fail = [&](const char *why) {
+    p.gett_ok = false;
+    p.gett_why = why;
+  };
+  if (p.spec.dtype != BES_FLOAT32 && p.spec.dtype != BES_FLOAT64) return fail("dtype");
+  if (e.n != 2) return fail("n != 2");
+  if (e.b > BES_GETT_MAX_B) return fail("b > 8");
+  for (const auto &l : e.ins)
+    if (has_repeat(l)) return fail("repeated index");
+  const int nidx = (int)e.extent.size();
+  for (int c = 0; c < nidx; ++c) {
+    const int cnt = contains(e.ins[0], c) + contains(e.ins[1], c) + contains(e.out, c);
+    if (cnt != 2) return fail("not a pure two-operand contraction");
+  }
+  GettRoles R;
+  R.posA = (!e.out.empty() && contains(e.ins[1], e.out[0]) && !contains(e.ins[0], e.out[0]))
+               ? 1 : 0;
+  R.posB = 1 - R.posA;
+  for (int c : e.out) (contains(e.ins[R.posA], c) ? R.Mi : R.Ni).push_back(c);
+  for (int c : e.ins[R.posA])
+    if (contains(e.ins[R.posB], c)) R.Ki.push_back(c);
+  for (int c : R.Mi) R.M *= e.extent[c];
+  for (int c : R.Ni) R.N *= e.extent[c];
+  for (int c : R.Ki) R.K *= e.extent[c];
+  // Linearize each group in its operand's memory order (largest stride
+  // first) so that consecutive tile rows or columns are consecutive
+  // addresses: M by A's strides, N by B's, K by A's unless only B is
+  // contiguous along K (first member's layout; the tables hold any order).
+  const int a0 = slot_arg(p, 0, R.posA), b0 = slot_arg(p, 0, R.posB);
+  auto by_stride = [&](std::vector<int> &g, int arg, int pos) {
+    std::stable_sort(g.begin(), g.end(), [&](int x, int y) {
+      int64_t sx = stride_of(p, arg, pos, 0, x), sy = stride_of(p, arg, pos, 0, y);
+      return (sx < 0 ? -sx : sx) > (sy < 0 ? -sy : sy);
+    });
+  };
+  auto unit_in = [&](const std::vector<int> &g, int arg, int pos) {
+    for (int c : g) {
+      const int64_t st = stride_of(p, arg, pos, 0, c);
+      if (st == 1 || st == -1) return true;
+    }
+    return false;
+  };
+  by_stride(R.Mi, a0, R.posA);
+  by_stride(R.Ni, b0, R.posB);
+  if (unit_in(R.Ki, b0, R.posB) && !unit_in(R.Ki, a0, R.posA)) by_stride(R.Ki, b0, R.posB);
+  else by_stride(R.Ki, a0, R.posA);
+  for (int k = 0; k < e.b; ++k)
+    for (int pos : {R.posA, R.posB}) {
+      const Operand &o = p.spec.args[slot_arg(p, k, pos)];
+      const bool affine = o.kind == BES_ELEMENTWISE && o.op == BES_OP_ID && o.nsrc == 1;
+      if (o.kind != BES_ARRAY && o.kind != BES_VIEW && !affine)
+        return fail("operands must be arrays, views or alpha*S+beta");
+    }
+  p.gt = R;
+  p.gett_ok = true;
+  p.gett_why.clear();
+}
+
 }  // namespace
+
+namespace {
+
+// Offsets of every multi-index of a group (last index fastest) for one set of
+// strides: out[l] = sum_d idx_d(l) * stride_d.
+void group_offsets(const std::vector<int64_t> &ext, const std::vector<int64_t> &st,
+                   std::vector<int64_t> &out) {
+  int64_t n = 1;
+  for (int64_t x : ext) n *= x;
+  const size_t base = out.size();
+  out.resize(base + (size_t)std::max<int64_t>(n, 1), 0);
+  if (n <= 0) return;
+  std::vector<int64_t> idx(ext.size(), 0);
+  int64_t off = 0;
+  for (int64_t l = 0; l < n; ++l) {
+    out[base + l] = off;
+    for (int d = (int)ext.size() - 1; d >= 0; --d) {
+      if (++idx[d] < ext[d]) {
+        off += st[d];
+        break;
+      }
+      off -= (ext[d] - 1) * st[d];
+      idx[d] = 0;
+    }
+  }
+}
+
+}  // namespace
+
+int bind_gett_static(const Plan &p, std::vector<int64_t> &tab, GettArgs &a, std::string &err) {
+  if (!p.gett_ok) {
+    err = "plan is not a binary contraction: " + p.gett_why;
+    return BES_E_UNSUPPORTED;
+  }
+  const GettRoles &R = p.gt;
+  const CanonEinsum &e = p.canon.form;
+  std::memset(&a, 0, sizeof a);
+  a.M = R.M;
+  a.N = R.N;
+  a.K = R.K;
+  a.n_members = e.b;
+  a.n_slots = p.n_slots;
+  tab.clear();
+  auto exts = [&](const std::vector<int> &g) {
+    std::vector<int64_t> x;
+    for (int c : g) x.push_back(e.extent[c]);
+    return x;
+  };
+  auto strides = [&](int arg, int pos, const std::vector<int> &g) {
+    std::vector<int64_t> x;
+    for (int c : g) x.push_back(stride_of(p, arg, pos, 0, c));
+    return x;
+  };
+  const std::vector<int64_t> eM = exts(R.Mi), eN = exts(R.Ni), eK = exts(R.Ki);
+  std::vector<int> order;
+  for (int sl = 0; sl < p.n_slots; ++sl)
+    for (int k = 0; k < e.b; ++k)
+      if (p.slot_of_member[p.canon.member_map[k]] == sl) order.push_back(k);
+  int m = 0;
+  for (int sl = 0; sl < p.n_slots; ++sl) {
+    GettSlot &S = a.slot[sl];
+    const std::vector<int64_t> ost = out_strides(p, sl);
+    auto ostride = [&](const std::vector<int> &g) {
+      std::vector<int64_t> x;
+      for (int c : g)
+        for (size_t d = 0; d < e.out.size(); ++d)
+          if (e.out[d] == c) x.push_back(ost[d]);
+      return x;
+    };
+    S.rowC = (int64_t)tab.size();
+    group_offsets(eM, ostride(R.Mi), tab);
+    S.colC = (int64_t)tab.size();
+    group_offsets(eN, ostride(R.Ni), tab);
+    S.acc = p.out_layout[sl].accumulate ? 1 : 0;
+    S.m0 = m;
+    for (int k : order) {
+      if (p.slot_of_member[p.canon.member_map[k]] != sl) continue;
+      GettMember &M = a.mem[m++];
+      const int aa = slot_arg(p, k, R.posA), bb = slot_arg(p, k, R.posB);
+      const Operand &oa = p.spec.args[aa], &ob = p.spec.args[bb];
+      M.rowA = (int64_t)tab.size();
+      group_offsets(eM, strides(aa, R.posA, R.Mi), tab);
+      M.colA = (int64_t)tab.size();
+      group_offsets(eK, strides(aa, R.posA, R.Ki), tab);
+      M.rowB = (int64_t)tab.size();
+      group_offsets(eK, strides(bb, R.posB, R.Ki), tab);
+      M.colB = (int64_t)tab.size();
+      group_offsets(eN, strides(bb, R.posB, R.Ni), tab);
+      const bool affA = oa.kind == BES_ELEMENTWISE, affB = ob.kind == BES_ELEMENTWISE;
+      M.a_alpha = affA ? oa.alpha : 1.0;
+      M.a_beta = affA ? oa.beta : 0.0;
+      M.b_alpha = affB ? ob.alpha : 1.0;
+      M.b_beta = affB ? ob.beta : 0.0;
+      // read each tile along the side on which the operand is contiguous
+      auto unit = [&](int64_t off) { return R.K > 1 && (tab[off + 1] - tab[off] == 1 ||
+                                                        tab[off + 1] - tab[off] == -1); };
+      M.a_kfast = unit(M.colA) ? 1 : 0;
+      M.b_nfast = unit(M.rowB) ? 0 : 1;
+    }
+    S.m1 = m;
+  }
+  return BES_OK;
+}
+
+void bind_gett_ptrs(const Plan &p, const void *const *src, void *const *out, GettArgs &a) {
+  const GettRoles &R = p.gt;
+  const CanonEinsum &e = p.canon.form;
+  const int64_t item = p.spec.dtype == BES_FLOAT64 ? 8 : 4;
+  std::vector<int> order;
+  for (int sl = 0; sl < p.n_slots; ++sl)
+    for (int k = 0; k < e.b; ++k)
+      if (p.slot_of_member[p.canon.member_map[k]] == sl) order.push_back(k);
+  int m = 0;
+  for (int sl = 0; sl < p.n_slots; ++sl) {
+    a.slot[sl].C = (char *)out[sl] +
+                   (p.out_layout[sl].custom ? p.out_layout[sl].offset * item : 0);
+    for (int k : order) {
+      if (p.slot_of_member[p.canon.member_map[k]] != sl) continue;
+      GettMember &M = a.mem[m++];
+      const int aa = slot_arg(p, k, R.posA), bb = slot_arg(p, k, R.posB);
+      M.A = (const char *)src[p.src_base[aa]] + p.spec.args[aa].src_offset[0] * item;
+      M.B = (const char *)src[p.src_base[bb]] + p.spec.args[bb].src_offset[0] * item;
+    }
+  }
+}
 
 bool template_supported(const Plan &p, int t) {
   switch (t) {
     case BES_T_FEM_STREAM: return p.fem_ok;
     case BES_T_MFMA: return p.mfma_ok && kMfmaTemplateReady;
+    case BES_T_GETT: return p.gett_ok;
     case BES_T_GENERIC:
       return (p.spec.dtype == BES_FLOAT32 || p.spec.dtype == BES_FLOAT64) &&
              p.spec.b <= BES_GEN_MAX_B && p.spec.n <= BES_GEN_MAX_OPS &&
@@ -447,6 +638,12 @@ bes_config default_config(const Plan &p) {
     c.p[1] = 64;   // blocks per CU in the grid: one tile per block at
                    // e = 2^20 (measured best for the lean kernel)
     c.p[2] = 0;    // lean kernel, two waves per tile, where the batch allows
+  } else if (p.gett_ok && std::min(p.gt.M, p.gt.N) >= 4 &&
+             p.gt.M * p.gt.N * std::max<int64_t>(p.gt.K, 1) >= ((int64_t)1 << 20)) {
+    // a contraction large enough to fill the 64 x 64 matrix-core tiles
+    c.template_id = BES_T_GETT;
+    c.p[0] = 64;
+    c.p[1] = 64;
   } else if (template_supported(p, BES_T_GENERIC)) {
     // Lanes per output grow with the shared contraction length (about 64
     // rows per lane; the generic template splits those rows across lanes and
@@ -530,6 +727,10 @@ int build_plan(Plan &p, std::string &err) {
     p.n_slots = p.spec.b;
   }
   p.out_layout.assign(p.n_slots, OutLayout());
+  p.exprs.clear();
+  for (const Operand &o : p.spec.args)
+    if (o.kind == BES_EXPR && std::find(p.exprs.begin(), p.exprs.end(), o.expr) == p.exprs.end())
+      p.exprs.push_back(o.expr);
   p.src_base.resize(p.spec.args.size());
   p.n_src = 0;
   for (size_t a = 0; a < p.spec.args.size(); ++a) {
@@ -538,6 +739,7 @@ int build_plan(Plan &p, std::string &err) {
   }
   analyse_fem(p);
   analyse_mfma(p);
+  analyse_gett(p);
   // A plan no template can evaluate (e.g. an integer dtype) still has a
   // canonical form and a key; launching it reports BES_E_UNSUPPORTED.
   p.cfg = default_config(p);
@@ -861,6 +1063,18 @@ int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std:
         put(L.so0, L.sc0, 2, sv);
         put(L.so1, L.sc1, 0, se);
         put(L.so1, L.sc1, 1, sc);
+      } else if (o.kind == BES_EXPR) {
+        // body `op` of the plan's list at (S0, S1); a one-source body reads
+        // S0 for s1 as well (an in-bounds value the body ignores)
+        L.kind = GEN_EXPR;
+        L.op = (int32_t)(std::find(p.exprs.begin(), p.exprs.end(), o.expr) - p.exprs.begin());
+        const int s1 = o.nsrc > 1 ? 1 : 0;
+        L.off0 = o.src_offset[0];
+        L.off1 = o.src_offset[s1];
+        for (int d = 0; d < o.ndim; ++d) {
+          put(L.so0, L.sc0, d, o.src_strides[0][d]);
+          put(L.so1, L.sc1, d, o.src_strides[s1][d]);
+        }
       } else {
         L.kind = o.kind != BES_ELEMENTWISE ? GEN_ARRAY
                  : (o.nsrc > 1 ? GEN_ELEMENTWISE2 : GEN_ELEMENTWISE);
@@ -1042,6 +1256,9 @@ int build_adjoint(const Plan &fwd, int pos, Plan &adj, int &n_out, std::string &
     }
     args.push_back(d);
   }
+  std::vector<const char *> exprs(args.size(), nullptr);
+  for (size_t a = 0; a < f.args.size(); ++a)
+    if (keep[a] >= 0 && f.args[a].kind == BES_EXPR) exprs[keep[a]] = f.args[a].expr.c_str();
   std::vector<int32_t> table;
   std::string nota;
   for (int c : f.out) nota += char('a' + c);
@@ -1059,7 +1276,7 @@ int build_adjoint(const Plan &fwd, int pos, Plan &adj, int &n_out, std::string &
   }
   adj = Plan();
   int rc = make_spec(nota.c_str(), f.b, f.n, (int)args.size(), args.data(), table.data(),
-                     adj.spec, err);
+                     adj.spec, err, exprs.data());
   if (rc) return rc;
   adj.adjoint = true;
   adj.slot_of_member = slot_of;

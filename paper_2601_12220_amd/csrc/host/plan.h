@@ -62,6 +62,14 @@ inline bool same_layouts(const std::vector<OutLayout> &a, const std::vector<OutL
   return true;
 }
 
+// GETT roles: C[M, N] = sum_K A[M, K] B[K, N] with index groups of any
+// strides (M and N in output order, K in A's axis order).
+struct GettRoles {
+  std::vector<int> Mi, Ni, Ki;  // canonical index ordinals
+  int posA = -1, posB = -1;
+  int64_t M = 1, N = 1, K = 1;
+};
+
 struct Plan {
   Spec spec;
   Canonical canon;
@@ -75,6 +83,9 @@ struct Plan {
   bool mfma_ok = false;
   std::string mfma_why;
   MfmaRoles mf;
+  bool gett_ok = false;
+  std::string gett_why;
+  GettRoles gt;
 
   // Output slots: member (user order) -> slot.  Regular plans: identity.
   // Adjoint plans sum the members of a slot.
@@ -88,6 +99,9 @@ struct Plan {
   bool adjoint = false;
   // Output layouts per slot (bes_plan_set_output).
   std::vector<OutLayout> out_layout;
+  // Distinct expression bodies of BES_EXPR arguments (GenLayout::op indexes
+  // this list); such plans run the generic template built at run time.
+  std::vector<std::string> exprs;
 
   // FEM-stream workspace for the packed shared operand (first FEM launch).
   mutable void *fem_ws = nullptr;
@@ -104,6 +118,14 @@ struct Plan {
     GenEinsum *dev = nullptr;
   };
   mutable std::vector<GenCopy> gen_cache;
+  // GETT offset tables, one device copy per (output layouts, device).
+  struct GettCopy {
+    std::vector<OutLayout> layouts;
+    int device = -1;
+    GettArgs args{};            // table offsets, flags and scalars; no pointers
+    int64_t *dev = nullptr;
+  };
+  mutable std::vector<GettCopy> gett_cache;
   // Profiling hook (bes_plan_set_timing): events recorded around the main
   // evaluation kernel(s) of every launch; caller-owned hipEvent_t handles.
   void *time_start = nullptr;
@@ -127,6 +149,11 @@ int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std:
 int bind_generic_ptrs(const Plan &p, const void *const *src, void *const *out, GenPtrs &ptrs);
 int bind_mfma(const Plan &p, const void *const *src, void *const *out, MfmaArgs &a,
               std::string &err);
+// GETT: the offset tables (host copy) and the pointer-free part of the
+// arguments; then the caller's pointers.
+int bind_gett_static(const Plan &p, std::vector<int64_t> &tables, GettArgs &a,
+                     std::string &err);
+void bind_gett_ptrs(const Plan &p, const void *const *src, void *const *out, GettArgs &a);
 
 // Dense row-major strides of the output in the notation's order.
 std::vector<int64_t> dense_out_strides(const Plan &p);

@@ -5,6 +5,8 @@
 // Definition "Batched Einstein Summation".
 #include "spec.h"
 
+#include <cctype>
+
 #include <cstring>
 
 namespace bes {
@@ -75,12 +77,99 @@ int parse_notation(const char *notation, std::vector<std::vector<int>> &ins,
 }
 
 static bool supported_kind(int k) {
-  return k == BES_ARRAY || k == BES_VIEW || k == BES_ELEMENTWISE || k == BES_TET_JACOBIAN;
+  return k == BES_ARRAY || k == BES_VIEW || k == BES_ELEMENTWISE || k == BES_TET_JACOBIAN ||
+         k == BES_EXPR;
+}
+
+bool valid_expression(const std::string &body, std::string &err) {
+  // A recognizer for: expr := term (('+'|'-'|'*'|'/') term)*;
+  // term := ('+'|'-')* (number | s0 | s1 | '(' expr ')' | func '(' args ')');
+  // args := expr (',' expr)*.  Tracked as a token-class state machine.
+  static const char *const kFuncs[] = {"sin", "cos", "tan", "exp", "log", "sqrt",
+                                       "fabs", "tanh", "pow", "fmin", "fmax"};
+  const size_t n = body.size();
+  if (n == 0 || n > 512) {
+    err = "expression body must have 1..512 characters";
+    return false;
+  }
+  std::vector<bool> call;   // per open parenthesis: a function call (allows ',')
+  bool want_operand = true;
+  size_t i = 0;
+  auto bad = [&](const std::string &why) {
+    err = why + " at position " + std::to_string(i) + " of \"" + body + "\"";
+    return false;
+  };
+  while (i < n) {
+    const char ch = body[i];
+    if (ch == ' ' || ch == '\t') {
+      ++i;
+      continue;
+    }
+    if (want_operand) {
+      if (ch == '+' || ch == '-') {
+        ++i;
+      } else if (ch == '(') {
+        call.push_back(false);
+        ++i;
+      } else if ((ch >= '0' && ch <= '9') || ch == '.') {
+        size_t j = i, digits = 0;
+        while (j < n && ((body[j] >= '0' && body[j] <= '9') || body[j] == '.')) {
+          digits += body[j] != '.';
+          ++j;
+        }
+        if (digits == 0) return bad("malformed number");
+        if (j < n && (body[j] == 'e' || body[j] == 'E')) {
+          ++j;
+          if (j < n && (body[j] == '+' || body[j] == '-')) ++j;
+          if (j >= n || body[j] < '0' || body[j] > '9') return bad("malformed number");
+          while (j < n && body[j] >= '0' && body[j] <= '9') ++j;
+        }
+        i = j;
+        want_operand = false;
+      } else if (std::isalpha((unsigned char)ch) || ch == '_') {
+        size_t j = i;
+        while (j < n && (std::isalnum((unsigned char)body[j]) || body[j] == '_')) ++j;
+        const std::string id = body.substr(i, j - i);
+        if (id == "s0" || id == "s1") {
+          i = j;
+          want_operand = false;
+        } else {
+          bool f = false;
+          for (const char *fn : kFuncs) f |= id == fn;
+          size_t k = j;
+          while (k < n && (body[k] == ' ' || body[k] == '\t')) ++k;
+          if (!f || k >= n || body[k] != '(') return bad("unknown name '" + id + "'");
+          call.push_back(true);
+          i = k + 1;
+        }
+      } else {
+        return bad(std::string("unexpected '") + ch + "'");
+      }
+    } else {
+      if (ch == '+' || ch == '-' || ch == '*' || ch == '/') {
+        want_operand = true;
+        ++i;
+      } else if (ch == ',') {
+        if (call.empty() || !call.back()) return bad("',' outside a function call");
+        want_operand = true;
+        ++i;
+      } else if (ch == ')') {
+        if (call.empty()) return bad("unbalanced ')'");
+        call.pop_back();
+        ++i;
+      } else {
+        return bad(std::string("unexpected '") + ch + "'");
+      }
+    }
+  }
+  if (want_operand) return bad("expression ends without an operand");
+  if (!call.empty()) return bad("unbalanced '('");
+  return true;
 }
 
 int make_spec(const char *notation, int b, int n, int n_args,
               const bes_operand *args, const int32_t *table, Spec &spec,
-              std::string &err) {
+              std::string &err, const char *const *exprs) {
   spec = Spec();
   if (b < 1 || b > BES_MAX_B) {
     err = "b out of range";
@@ -125,8 +214,8 @@ int make_spec(const char *notation, int b, int n, int n_args,
       err = "unknown dtype";
       return BES_E_INVALID;
     }
-    int want_src = (o.kind == BES_ELEMENTWISE && o.nsrc == 2) ? 2 : 1;
-    if (o.nsrc != want_src && !(o.kind == BES_ELEMENTWISE && o.nsrc == 1)) {
+    int want_src = ((o.kind == BES_ELEMENTWISE || o.kind == BES_EXPR) && o.nsrc == 2) ? 2 : 1;
+    if (o.nsrc != want_src) {
       err = "bad source count for operand kind";
       return BES_E_INVALID;
     }
@@ -137,6 +226,14 @@ int make_spec(const char *notation, int b, int n, int n_args,
     if (o.kind == BES_TET_JACOBIAN && (o.ndim != 3 || o.shape[1] != 3 || o.shape[2] != 3)) {
       err = "tetrahedron Jacobian operands have shape (e,3,3)";
       return BES_E_INVALID;
+    }
+    if (o.kind == BES_EXPR) {
+      if (!exprs || !exprs[a]) {
+        err = "expression operand " + std::to_string(a) + " has no body";
+        return BES_E_INVALID;
+      }
+      d.expr = exprs[a];
+      if (!valid_expression(d.expr, err)) return BES_E_INVALID;
     }
     d.kind = o.kind;
     d.dtype = o.dtype;

@@ -28,6 +28,7 @@ struct Operand {
   int32_t op = BES_OP_ID;
   double alpha = 1.0;
   double beta = 0.0;
+  std::string expr;   // body of a BES_EXPR operand over s0, s1
 };
 
 struct Spec {
@@ -51,9 +52,14 @@ int parse_notation(const char *notation, std::vector<std::vector<int>> &ins,
 // Build and validate a spec from ABI inputs: soundness conditions after
 // Eq. (1), one extent per index across the batch, every argument used,
 // distinct output indices (C27), common dtype.  Fills dense source strides.
+// exprs (may be NULL) holds the body of every BES_EXPR argument.
 int make_spec(const char *notation, int b, int n, int n_args,
               const bes_operand *args, const int32_t *table, Spec &spec,
-              std::string &err);
+              std::string &err, const char *const *exprs = nullptr);
+
+// Is `body` an expression the run-time build accepts: s0, s1, decimal
+// constants, + - * / ( ) , and the functions listed in bes.h?
+bool valid_expression(const std::string &body, std::string &err);
 
 const char *dtype_name(int dtype);  // "f64", "f32", ...
 

@@ -50,6 +50,12 @@ hipError_t launch_persistent(bool f64, const GenEinsum *table, const GenPtrs *pt
 // captured graph replays it correctly).
 hipError_t launch_fill_zero(void *p, int64_t n, int elem_bytes, hipStream_t stream);
 
+// GETT template (FP32 / FP64 matrix cores): `a.tab` points to the device
+// offset tables the host built for the plan.  `ksplit` = K ranges per output
+// tile (0: chosen from the tile count and K; > 1 zeroes the overwritten
+// outputs first, then adds partial tiles atomically).
+hipError_t launch_gett(bool f64, const GettArgs &a, int ksplit, hipStream_t stream);
+
 // MFMA dense-contraction template (FP32).  mfma_args_ok: the shape and the
 // alignment of every operand fit the template's vector tile loads.
 bool mfma_args_ok(const MfmaArgs &a);

@@ -22,6 +22,7 @@ from . import capi
 T_FEM_STREAM = 1
 T_GENERIC = 2
 T_MFMA = 3
+T_GETT = 4
 
 
 def candidates(template_id: int) -> List[Tuple[int, ...]]:
@@ -32,7 +33,8 @@ def candidates(template_id: int) -> List[Tuple[int, ...]]:
                 1 descriptor-driven).
     Generic:    p[0] = outputs per tile, p[1] = lanes per output, p[2] = chunks
                 of the shared contracted space (their sums add into the output).
-    MFMA:       the single 128 x 128 tile shape the template implements."""
+    MFMA:       the single 128 x 128 tile shape the template implements.
+    GETT:       64 x 64 tiles; p[2] = K ranges per output tile."""
     if template_id == T_FEM_STREAM:
         return [(T_FEM_STREAM, 64, b, v) for v in (0, 2, 1) for b in (8, 16, 32, 64)]
     if template_id == T_GENERIC:
@@ -41,6 +43,8 @@ def candidates(template_id: int) -> List[Tuple[int, ...]]:
                 + [(T_GENERIC, 256, lanes, split) for lanes in (16, 64) for split in (8, 64)])
     if template_id == T_MFMA:
         return [(T_MFMA, 128, 128)]
+    if template_id == T_GETT:   # p[2]: K ranges per output tile (0: launcher's choice)
+        return [(T_GETT, 64, 64, ks) for ks in (0, 1, 4, 16, 64)]
     return []
 
 

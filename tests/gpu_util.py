@@ -28,6 +28,14 @@ def materialize(w, name):
         return F.elementwise(s0, o.op, o.alpha, o.beta, s1)
     if o.kind == "tet_jacobian":
         return F.tet_jacobian(src[0].reshape(-1, 4, 3))
+    if o.kind == "expr":
+        views = []
+        for k, s in enumerate(src):
+            if k == 0 and o.strides is not None:
+                views.append(F.strided_view(s, o.shape, o.strides, o.offset))
+            else:
+                views.append(s.reshape(o.shape))
+        return F.expression(o.expr, views[0], views[1] if len(views) > 1 else None)
     raise ValueError(o.kind)
 
 

@@ -291,3 +291,15 @@ def test_local_divergence_of_a_constant_field_is_zero():
     vals["U0"] = U
     got = oracle.batched_einsum(w.notation, w.table, vals)
     assert np.abs(got[0]).max() < 1e-13
+
+
+def test_affine_binary_contraction_against_numpy():
+    # (alpha_1 A + beta_1)(alpha_2 B + beta_2) contracted: the oracle on the
+    # functional operands against numpy.einsum on hand-materialized ones
+    import workloads
+    from tests.gpu_util import oracle_full
+    w = workloads.tccg_like(3, min_elems=1 << 8, max_elems=1 << 12)
+    A, B = w.buffers["A"].numpy(), w.buffers["B"].numpy()
+    oa, ob = w.operands["Ax"], w.operands["Bx"]
+    ref = np.einsum(w.notation, oa.alpha * A + oa.beta, ob.alpha * B + ob.beta)
+    np.testing.assert_allclose(oracle_full(w)[0], ref, rtol=1e-12, atol=1e-12)

@@ -15,6 +15,7 @@ Operand kinds (what the library calls functional operands):
 * ``view``         M(A)[idx] = S0[offset + sum idx_k * strides_k]
 * ``elementwise``  M(A)[idx] = alpha * op(S0[idx]) + beta (+ S1[idx])
 * ``tet_jacobian`` M(A)[e, x, r] from vertex coordinates S0[e, 4, 3]
+* ``expr``         M(A)[idx] = body(S0[idx], S1[idx]) for an expression body
 """
 from __future__ import annotations
 
@@ -44,6 +45,7 @@ class Operand:
     op: str = "id"                   # elementwise: id | sin | cos | square
     alpha: float = 1.0
     beta: float = 0.0
+    expr: Optional[str] = None       # expr: body over s0, s1 (e.g. "3*cos(s0)+5")
 
 
 @dataclass
@@ -191,6 +193,57 @@ def local_divergence(p: int = 3, e: int = 100_000, b: int = 1,
         table.append(["J", "D", f"U{k}"])
     return Workload(f"local_div_p{p}", "xre,rij,xej->ei", table, ops, bufs, dtype,
                     {"e": e, "ni": n, "nj": n, "p": p})
+
+
+# ---------------------------------------------------------------------------
+# Binary contractions with affine operands (alpha_1 A + beta_1)(alpha_2 B +
+# beta_2), the extension of the TCCG suite in Section "TCCG Benchmark suite
+# with Unmaterialized Operands".  The suite itself is not available here: a
+# seeded generator draws contractions of the same kind -- 1-3 free indices
+# per operand, 1-3 contracted indices, operand and output axes in random
+# orders (the transpositions that make them tensor contractions rather than
+# GEMMs), extents multiples of 8, the largest tensor of 2^20 - 2^24 elements
+# -- with FP64 data and runtime scalars.
+# ---------------------------------------------------------------------------
+
+TCCG_EXTENTS = (8, 16, 24, 32, 48, 64, 72, 96)
+
+
+def tccg_like(case: int, dtype: str = "float64", affine: bool = True,
+              max_elems: int = 1 << 24, min_elems: int = 1 << 20) -> Workload:
+    rng = random.Random(SEED_BASE + 800 + case)
+    while True:
+        na, nb, nk = rng.randint(1, 3), rng.randint(1, 3), rng.randint(1, 3)
+        if na + nb + nk > 6:
+            continue
+        letters = rng.sample(string.ascii_lowercase[:12], na + nb + nk)
+        fa, fb, kk = letters[:na], letters[na:na + nb], letters[na + nb:]
+        ext = {c: rng.choice(TCCG_EXTENTS) for c in letters}
+        size = lambda ls: _prod(ext[c] for c in ls)    # noqa: E731
+        big = max(size(fa + kk), size(kk + fb), size(fa + fb))
+        if min_elems <= big <= max_elems:
+            break
+    A = fa + kk
+    B = kk + fb
+    rng.shuffle(A)
+    rng.shuffle(B)
+    out = fa + fb
+    rng.shuffle(out)
+    notation = "".join(A) + "," + "".join(B) + "->" + "".join(out)
+    bufs = {"A": _normal(8, 2 * case, tuple(ext[c] for c in A), dtype),
+            "B": _normal(8, 2 * case + 1, tuple(ext[c] for c in B), dtype)}
+    ops = {}
+    for nm in ("A", "B"):
+        shape = tuple(bufs[nm].shape)
+        if affine:
+            alpha = round(rng.uniform(0.5, 2.0), 3)
+            beta = round(rng.uniform(-1.0, 1.0), 3)
+            ops[nm + "x"] = Operand(nm + "x", shape, dtype, "elementwise", (nm,),
+                                    op="id", alpha=alpha, beta=beta)
+        else:
+            ops[nm + "x"] = Operand(nm + "x", shape, dtype, "array", (nm,))
+    return Workload(f"tccg_like_{case}", notation, [["Ax", "Bx"]], ops, bufs, dtype,
+                    {"ext": ext, "free_a": na, "free_b": nb, "contracted": nk})
 
 
 # ---------------------------------------------------------------------------
