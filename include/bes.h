@@ -116,7 +116,10 @@ enum bes_template {
                             variant: 0 the lean kernel with two waves per
                             64-element tile where the batch allows it, 2 the
                             lean kernel with one wave per tile, 1 always the
-                            descriptor-driven kernel */
+                            descriptor-driven kernel; for the face-mass /
+                            divergence class p[1] = blocks of four waves
+                            per compute unit, p[2] = 0 or 1 the shared
+                            matrix in LDS, 2 as scalar operands */
   BES_T_GENERIC = 2,     /* any batched einsum; p[0] = outputs per tile,
                             p[1] = lanes per output (1,2,4,...,64),
                             p[2] = chunks of the shared contracted index
@@ -127,10 +130,13 @@ enum bes_template {
                             matrix cores: arbitrary index groups and strides
                             through offset tables, affine operands
                             alpha*A+beta applied while loading, ragged
-                            edges; p[0] = tile M, p[1] = tile N (64),
+                            edges; p[0], p[1] unused (64),
                             p[2] = K ranges per output tile (0: chosen by
                             the launcher; > 1: partial tiles add
-                            atomically into the zeroed output) */
+                            atomically into the zeroed output), p[3] =
+                            tile shape (0: by the output's extents; 1: 16
+                            x 128, 2: 32 x 128, 3: 128 x 32, 4: 128 x 16,
+                            5: 64 x 64) */
 };
 
 typedef struct bes_config {
@@ -319,6 +325,16 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count,
 int bes_batch_launch(bes_batch *batch, const void *const *const *src_ptrs,
                      void *const *const *out_ptrs, void *hip_stream);
 void bes_batch_destroy(bes_batch *batch);
+
+/* bes_batch_launch in two parts, for callers that launch the same batch on
+ * the same buffers many times: bes_batch_bind binds the pointers (as
+ * bes_batch_launch does; the device copy is refreshed on `hip_stream` only
+ * when a pointer changed) and bes_batch_replay launches the persistent work
+ * on `hip_stream` with the pointers bound last, without touching the 256
+ * per-plan pointer sets again.  BES_E_STATE if nothing was bound yet. */
+int bes_batch_bind(bes_batch *batch, const void *const *const *src_ptrs,
+                   void *const *const *out_ptrs, void *hip_stream);
+int bes_batch_replay(bes_batch *batch, void *hip_stream);
 
 /* Adjoint: the batched einsum giving d<G, R>/dA for the arguments at operand
  * position `pos` of a forward plan.  Its operands are, per forward member i,

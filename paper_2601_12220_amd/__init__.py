@@ -233,3 +233,11 @@ class Batch:
 
     def launch_ptrs(self, srcs, outs, stream: int = 0):
         capi.bes_batch_launch(self.h, srcs, outs, stream)
+
+    def bind_ptrs(self, srcs, outs, stream: int = 0):
+        """Bind device pointers once (bes_batch_bind); replay() then launches
+        on them without marshalling 256 pointer lists per launch."""
+        capi.bes_batch_bind(self.h, srcs, outs, stream)
+
+    def replay(self, stream: int = 0):
+        capi.bes_batch_replay(self.h, stream)

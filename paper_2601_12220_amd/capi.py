@@ -107,6 +107,8 @@ def load():
         "bes_batch_create": ([P, PP, i32, PP], i32),
         "bes_batch_launch": ([P, ctypes.POINTER(PP), ctypes.POINTER(PP), P], i32),
         "bes_batch_destroy": ([P], None),
+        "bes_batch_bind": ([P, ctypes.POINTER(PP), ctypes.POINTER(PP), P], i32),
+        "bes_batch_replay": ([P, P], i32),
         "bes_adjoint": ([P, P, i32, PP, i32p], i32),
         "bes_plan_set_output": ([P, i32, ctypes.c_int64, i64p, i32], i32),
         "bes_fill_zero": ([P, ctypes.c_int64, i32, P], i32),
@@ -288,13 +290,27 @@ def bes_batch_create(ctx, plans):
     return h
 
 
-def bes_batch_launch(h, src_lists, out_lists, stream: int = 0, _keep=None) -> None:
+def _ptr_lists(src_lists, out_lists):
     srcs = [_ptrs(s) for s in src_lists]
     outs = [_ptrs(o) for o in out_lists]
     PP = ctypes.POINTER(ctypes.c_void_p)
     sarr = (PP * len(srcs))(*[ctypes.cast(s, PP) for s in srcs])
     oarr = (PP * len(outs))(*[ctypes.cast(o, PP) for o in outs])
+    return sarr, oarr, (srcs, outs)
+
+
+def bes_batch_launch(h, src_lists, out_lists, stream: int = 0, _keep=None) -> None:
+    sarr, oarr, _ = _ptr_lists(src_lists, out_lists)
     check(load().bes_batch_launch(h, sarr, oarr, ctypes.c_void_p(stream)), "bes_batch_launch")
+
+
+def bes_batch_bind(h, src_lists, out_lists, stream: int = 0) -> None:
+    sarr, oarr, _ = _ptr_lists(src_lists, out_lists)
+    check(load().bes_batch_bind(h, sarr, oarr, ctypes.c_void_p(stream)), "bes_batch_bind")
+
+
+def bes_batch_replay(h, stream: int = 0) -> None:
+    check(load().bes_batch_replay(h, ctypes.c_void_p(stream)), "bes_batch_replay")
 
 
 def bes_batch_destroy(h) -> None:

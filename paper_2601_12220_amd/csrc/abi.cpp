@@ -49,6 +49,7 @@ struct bes_batch {
   hipGraphExec_t exec = nullptr;
   bool use_graph = true;
   bool any_split = false;
+  bool narrow = true;   // every plan's descriptor decodes in 32 bits
 };
 
 namespace {
@@ -435,12 +436,12 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
     if (rc) return fail(rc, err);
     GenPtrs ptrs;
     bes::bind_generic_ptrs(p, src.data(), out_ptrs, ptrs);
-    hipFunction_t jk = nullptr, jz = nullptr;
-    if (!p.exprs.empty() && (rc = bes::jit_generic(f64, p.exprs, &jk, &jz, err)) != BES_OK)
+    bes::JitKernels jk;
+    if (!p.exprs.empty() && (rc = bes::jit_generic(f64, p.exprs, &jk, err)) != BES_OK)
       return fail(rc, err);
     if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
     e = p.exprs.empty() ? bes::launch_generic(f64, gd->dev, *gd->host, ptrs, stream)
-                        : bes::launch_generic_jit(jk, jz, gd->dev, *gd->host, ptrs, stream);
+                        : bes::launch_generic_jit(jk, gd->dev, *gd->host, ptrs, stream);
     if (e != hipSuccess) return hip_fail(e, "generic launch");
     if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
     return BES_OK;
@@ -448,26 +449,13 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
   switch (p.cfg.template_id) {
     case BES_T_FEM_STREAM: {
       if (bes::any_accumulate(p)) return run_generic(p.cfg);
-      if (p.fem.cls == 1) {
-        FemApplyArgs a;
-        int rc = bes::bind_fem_apply(p, src.data(), out_ptrs, a, err);
-        if (rc) return fail(rc, err);
-        e = bes::launch_fem_apply(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, p.fem.diag, a,
-                                  p.cfg.p[1], stream, (hipEvent_t)p.time_start,
-                                  (hipEvent_t)p.time_stop);
-        if (e != hipSuccess) return hip_fail(e, "FEM-stream apply launch");
-        return BES_OK;
-      }
-      FemArgs a;
-      int rc = bes::bind_fem(p, src.data(), out_ptrs, a, err);
-      if (rc) return fail(rc, err);
       int dev = 0;
       if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
       if (p.fem_ws && p.fem_ws_device != dev) {
         (void)hipFree(p.fem_ws);
         p.fem_ws = nullptr;
       }
-      if (!p.fem_ws) {
+      if (!p.fem_ws) {   // re-laid S (both classes; sized for the larger need)
         size_t bytes = bes::fem_workspace_bytes(f64, p.fem.NI, p.fem.NJ, p.fem.NR);
         if ((e = hipMalloc(&p.fem_ws, bytes)) != hipSuccess) {
           p.fem_ws = nullptr;
@@ -475,6 +463,19 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
         }
         p.fem_ws_device = dev;
       }
+      if (p.fem.cls == 1) {
+        FemApplyArgs a;
+        int rc = bes::bind_fem_apply(p, src.data(), out_ptrs, a, err);
+        if (rc) return fail(rc, err);
+        e = bes::launch_fem_apply(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, p.fem.diag, a,
+                                  p.fem_ws, p.cfg.p[1], p.cfg.p[2], stream,
+                                  (hipEvent_t)p.time_start, (hipEvent_t)p.time_stop);
+        if (e != hipSuccess) return hip_fail(e, "FEM-stream apply launch");
+        return BES_OK;
+      }
+      FemArgs a;
+      int rc = bes::bind_fem(p, src.data(), out_ptrs, a, err);
+      if (rc) return fail(rc, err);
       e = bes::launch_fem(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, a, p.fem_ws, p.cfg.p[1],
                           p.cfg.p[2], stream, (hipEvent_t)p.time_start,
                           (hipEvent_t)p.time_stop);
@@ -506,7 +507,7 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
       a.tab = gc->dev;
       bes::bind_gett_ptrs(p, src.data(), out_ptrs, a);
       if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
-      e = bes::launch_gett(f64, a, p.cfg.p[2], stream);
+      e = bes::launch_gett(f64, a, p.cfg.p[3], p.cfg.p[2], stream);
       if (e != hipSuccess) return hip_fail(e, "GETT launch");
       if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
       return BES_OK;
@@ -536,21 +537,23 @@ int bes_launch_noalloc(const bes_plan *plan, const void *const *src_ptrs, void *
     case BES_T_FEM_STREAM: {
       if (bes::any_accumulate(p))
         return fail(BES_E_UNSUPPORTED, "no-alloc launch: the FEM-stream template overwrites");
-      if (p.fem.cls == 1) {   // the apply class needs no scratch
-        FemApplyArgs a;
-        int rc = bes::bind_fem_apply(p, src.data(), out_ptrs, a, err);
-        if (rc) return fail(rc, err);
-        e = bes::launch_fem_apply(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, p.fem.diag, a,
-                                  p.cfg.p[1], stream, (hipEvent_t)p.time_start,
-                                  (hipEvent_t)p.time_stop);
-        if (e != hipSuccess) return hip_fail(e, "FEM-stream apply launch");
-        return BES_OK;
-      }
       const size_t need = bes::fem_workspace_bytes(f64, p.fem.NI, p.fem.NJ, p.fem.NR);
       if (need > kScratchBytes)
         return fail(BES_E_UNSUPPORTED, "no-alloc launch: the shared operand needs " +
                                            std::to_string(need) + " bytes of scratch, more than " +
                                            std::to_string(kScratchBytes));
+      if (p.fem.cls == 1) {
+        FemApplyArgs a;
+        int rc = bes::bind_fem_apply(p, src.data(), out_ptrs, a, err);
+        if (rc) return fail(rc, err);
+        void *ws = nullptr;
+        if ((rc = scratch_of_current_device(&ws)) != BES_OK) return rc;
+        e = bes::launch_fem_apply(f64, p.fem.NI, p.fem.NJ, p.fem.NR, p.fem.NX, p.fem.diag, a, ws,
+                                  p.cfg.p[1], p.cfg.p[2], stream, (hipEvent_t)p.time_start,
+                                  (hipEvent_t)p.time_stop);
+        if (e != hipSuccess) return hip_fail(e, "FEM-stream apply launch");
+        return BES_OK;
+      }
       FemArgs a;
       int rc = bes::bind_fem(p, src.data(), out_ptrs, a, err);
       if (rc) return fail(rc, err);
@@ -666,6 +669,7 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
     B->plans.push_back(&p);
     const GenEinsum &g = table[k];
     if (g.split > 1) B->any_split = true;
+    if (!g.narrow) B->narrow = false;
     // Work per output of the factored evaluation: the shared rows times the
     // exclusive sums of the operands that depend on them, plus the others.
     double per = 0.0, once = 0.0;
@@ -729,6 +733,12 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
 
 int bes_batch_launch(bes_batch *B, const void *const *const *src_ptrs, void *const *const *out_ptrs,
                      void *hip_stream) {
+  int rc = bes_batch_bind(B, src_ptrs, out_ptrs, hip_stream);
+  return rc < 0 ? rc : bes_batch_replay(B, hip_stream);
+}
+
+int bes_batch_bind(bes_batch *B, const void *const *const *src_ptrs, void *const *const *out_ptrs,
+                   void *hip_stream) {
   if (!B || !src_ptrs || !out_ptrs) return fail(BES_E_INVALID, "NULL argument");
   hipStream_t stream = (hipStream_t)hip_stream;
   const int count = (int)B->plans.size();
@@ -755,12 +765,20 @@ int bes_batch_launch(bes_batch *B, const void *const *const *src_ptrs, void *con
     B->last = cur;
     B->have_last = true;
   }
+  return BES_OK;
+}
+
+int bes_batch_replay(bes_batch *B, void *hip_stream) {
+  if (!B) return fail(BES_E_INVALID, "NULL batch");
+  if (!B->have_last) return fail(BES_E_STATE, "bind pointers before the first replay");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  hipError_t e;
   if (B->use_graph && !B->exec) {
     bool ok = hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       hipError_t le = bes::launch_persistent(B->f64, B->d_table, B->d_ptrs, B->d_items, B->n_items,
                                              B->d_counters, B->grid, B->capture_stream,
-                                             (int)B->plans.size(), B->any_split);
+                                             (int)B->plans.size(), B->any_split, B->narrow);
       hipGraph_t g = nullptr;
       hipError_t ce = hipStreamEndCapture(B->capture_stream, &g);
       ok = le == hipSuccess && ce == hipSuccess && g;
@@ -782,7 +800,7 @@ int bes_batch_launch(bes_batch *B, const void *const *const *src_ptrs, void *con
     return BES_OK;
   }
   e = bes::launch_persistent(B->f64, B->d_table, B->d_ptrs, B->d_items, B->n_items, B->d_counters,
-                             B->grid, stream, (int)B->plans.size(), B->any_split);
+                             B->grid, stream, (int)B->plans.size(), B->any_split, B->narrow);
   if (e != hipSuccess) return hip_fail(e, "persistent launch");
   return BES_OK;
 }

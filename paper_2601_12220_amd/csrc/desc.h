@@ -156,7 +156,14 @@ typedef struct GenEinsum {
   int64_t o_str[BES_GEN_MAX_B][BES_GEN_MAX_IDX];
   int32_t o_acc[BES_GEN_MAX_B];
   int32_t o_dense;                       // every slot dense, offset 0, overwrite
-  int32_t pad3;
+  // Division by the extents with precomputed multipliers: for a dividend
+  // x < 2^31, x / ext = (umulhi(x, mul) + x) >> shift (round-up method of
+  // Granlund and Montgomery).  `narrow`: every linear index of the
+  // descriptor is below 2^31, so the kernels decode with these 32-bit
+  // multiplications instead of 64-bit divisions.
+  int32_t narrow;
+  uint32_t out_mul[BES_GEN_MAX_IDX], con_mul[BES_GEN_MAX_IDX];
+  int32_t out_shift[BES_GEN_MAX_IDX], con_shift[BES_GEN_MAX_IDX];
   int32_t layout[BES_GEN_MAX_B][BES_GEN_MAX_OPS];  // layout id per (member, op)
   int32_t slot_of[BES_GEN_MAX_B];                  // member -> output slot
   int32_t slot_m0[BES_GEN_MAX_B], slot_m1[BES_GEN_MAX_B];  // members of slot,

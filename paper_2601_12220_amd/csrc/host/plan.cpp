@@ -1024,6 +1024,34 @@ int bind_generic_static(const Plan &p, const bes_config &cfg, GenEinsum &g, std:
     g.ex_size[j] = 1;
     for (int d = 0; d < g.ex_n[j]; ++d) g.ex_size[j] *= g.con_ext[g.ex_off[j] + d];
   }
+  // 32-bit decoding: multipliers for every extent, each checked at the
+  // edges of its range (any failure keeps the 64-bit path)
+  const int64_t lim = (int64_t)1 << 31;
+  bool narrow = g.out_size < lim && g.sh_size < lim;
+  for (int k = 0; k < s.n; ++k) narrow = narrow && g.ex_size[k] < lim;
+  auto magic = [&](int64_t ext, uint32_t &mul, int32_t &shift) {
+    if (ext <= 1) {
+      mul = 1;
+      shift = 0;
+      return true;
+    }
+    int l = 0;
+    while (((int64_t)1 << l) < ext) ++l;
+    mul = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - (uint64_t)ext)) / (uint64_t)ext +
+                     1);
+    shift = l;
+    for (uint32_t x : {0u, (uint32_t)ext - 1, (uint32_t)ext, 2u * (uint32_t)ext - 1,
+                       (uint32_t)(lim - 1)}) {
+      const uint32_t hi = (uint32_t)(((uint64_t)x * mul) >> 32);
+      if ((uint32_t)((hi + x) >> shift) != x / (uint32_t)ext) return false;
+    }
+    return true;
+  };
+  for (int d = 0; d < BES_GEN_MAX_IDX; ++d) {
+    if (d < g.n_out) narrow = narrow && magic(g.out_ext[d], g.out_mul[d], g.out_shift[d]);
+    if (d < g.n_con) narrow = narrow && magic(g.con_ext[d], g.con_mul[d], g.con_shift[d]);
+  }
+  g.narrow = narrow ? 1 : 0;
   g.tile = cfg.p[0] > 0 ? cfg.p[0] : 256;
   g.lanes = cfg.p[1] > 0 ? cfg.p[1] : 1;
   g.split = cfg.p[2] > 0 ? cfg.p[2] : 1;

@@ -59,25 +59,42 @@ constexpr int kJC = (NJ % 5 == 0) ? 5 : (NJ % 4 == 0 ? 4 : (NJ <= 6 ? NJ : 1));
 template <int NI>
 constexpr int kNIP = (NI + 1) & ~1;   // S rows padded to an even length
 
-template <typename T, int NI, int NJ, int NC, int NX, bool DIAG, bool EW>
+// S re-laid as [c][j][i] (rows padded to NIP) for the scalar-operand
+// variant, which reads it through the scalar data cache.
+template <typename T>
+__global__ void __launch_bounds__(256) apply_pack_kernel(const FemApplyArgs a, T *__restrict__ dst,
+                                                         int NI, int NJ, int NC, int NIP) {
+  const T *__restrict__ S = (const T *)a.S;
+  for (int f = blockIdx.x * 256 + threadIdx.x; f < NC * NJ * NIP; f += gridDim.x * 256) {
+    const int i = f % NIP, cj = f / NIP;
+    const int c = cj / NJ, j = cj - c * NJ;
+    dst[f] = i < NI ? S[c * a.ss[0] + i * a.ss[1] + j * a.ss[2]] : (T)0;
+  }
+}
+
+// SREG: S is read from the packed copy `Sp` at wave-uniform addresses, so it
+// reaches the FMAs through the scalar data cache as scalar operands (for S
+// that fits in that cache); otherwise S sits in LDS and every lane reads the
+// same address (a broadcast).
+template <typename T, int NI, int NJ, int NC, int NX, bool DIAG, bool EW, bool SREG>
 __global__ void __launch_bounds__(kWaves * kTile)
-    fem_apply_kernel(const FemApplyArgs a, int64_t n_items) {
+    fem_apply_kernel(const FemApplyArgs a, const T *__restrict__ Sp, int64_t n_items) {
   constexpr int JC = kJC<NJ>;
   constexpr int NIP = kNIP<NI>;
   constexpr int NG = DIAG ? NC : NX * NC;     // geometry values per element
-  __shared__ T S_l[NC * NJ * NIP];
+  __shared__ T S_l[SREG ? 2 : NC * NJ * NIP];
   __shared__ T X_l[kWaves][NX * JC * kPitch];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // S into LDS as [c][j][i] from the caller's strides (once per block).
-  {
+  if constexpr (!SREG) {
     const T *__restrict__ S = (const T *)a.S;
     for (int f = threadIdx.x; f < NC * NJ * NIP; f += kWaves * kTile) {
       const int i = f % NIP, cj = f / NIP;
       const int c = cj / NJ, j = cj - c * NJ;
       S_l[f] = i < NI ? S[c * a.ss[0] + i * a.ss[1] + j * a.ss[2]] : (T)0;
     }
+    __syncthreads();
   }
-  __syncthreads();
   T *__restrict__ X = X_l[wave];
   const int b = a.n_members;
   const T alpha = (T)a.alpha, beta = (T)a.beta;
@@ -165,7 +182,8 @@ __global__ void __launch_bounds__(kWaves * kTile)
 #pragma unroll
             for (int x = 1; x < NX; ++x) w = fma(g[x * NC + c], u[x], w);
           }
-          const T *__restrict__ srow = &S_l[(c * NJ + jc + jj) * NIP];
+          const T *__restrict__ srow = SREG ? Sp + (c * NJ + jc + jj) * NIP
+                                            : &S_l[(c * NJ + jc + jj) * NIP];
 #pragma unroll
           for (int i = 0; i < NI; ++i) y[i] = fma(srow[i], w, y[i]);
         }
@@ -181,35 +199,67 @@ __global__ void __launch_bounds__(kWaves * kTile)
 }
 
 template <typename T, int NI, int NJ, int NC, int NX, bool DIAG>
-hipError_t launch_apply_shape(const FemApplyArgs &a, int blocks_per_cu, hipStream_t stream) {
+hipError_t launch_apply_shape(const FemApplyArgs &a, const T *Sp, int blocks_per_cu,
+                              bool sreg, hipStream_t stream) {
   const int64_t tiles = (a.E + kTile - 1) / kTile;
   const int64_t items = tiles * a.n_members;
   const int64_t cap = (int64_t)device_cu_count() * std::max(1, blocks_per_cu);
   const int64_t blocks = std::min<int64_t>((items + kWaves - 1) / kWaves, cap);
-  // the functional-operand prologue has its own instantiation, so the plain
+  const dim3 grid((unsigned)blocks), block(kWaves * kTile);
+  // the functional-operand prologue has its own instantiations, so the plain
   // path carries none of its code or registers
-  if (a.u_kind == FEM_SRC_ELEMENTWISE)
-    hipLaunchKernelGGL((fem_apply_kernel<T, NI, NJ, NC, NX, DIAG, true>),
-                       dim3((unsigned)blocks), dim3(kWaves * kTile), 0, stream, a, items);
+  const bool ew = a.u_kind == FEM_SRC_ELEMENTWISE;
+  if (ew && sreg)
+    hipLaunchKernelGGL((fem_apply_kernel<T, NI, NJ, NC, NX, DIAG, true, true>), grid, block, 0,
+                       stream, a, Sp, items);
+  else if (ew)
+    hipLaunchKernelGGL((fem_apply_kernel<T, NI, NJ, NC, NX, DIAG, true, false>), grid, block, 0,
+                       stream, a, Sp, items);
+  else if (sreg)
+    hipLaunchKernelGGL((fem_apply_kernel<T, NI, NJ, NC, NX, DIAG, false, true>), grid, block, 0,
+                       stream, a, Sp, items);
   else
-    hipLaunchKernelGGL((fem_apply_kernel<T, NI, NJ, NC, NX, DIAG, false>),
-                       dim3((unsigned)blocks), dim3(kWaves * kTile), 0, stream, a, items);
+    hipLaunchKernelGGL((fem_apply_kernel<T, NI, NJ, NC, NX, DIAG, false, false>), grid, block, 0,
+                       stream, a, Sp, items);
   return hipGetLastError();
 }
 
 }  // namespace
 
+size_t fem_apply_workspace_bytes(bool f64, int NI, int NJ, int NC) {
+  return (size_t)NC * NJ * ((NI + 1) & ~1) * (f64 ? 8 : 4);
+}
+
 hipError_t launch_fem_apply(bool f64, int NI, int NJ, int NC, int NX, bool diag,
-                            const FemApplyArgs &a, int blocks_per_cu, hipStream_t stream,
-                            hipEvent_t ev_start, hipEvent_t ev_stop) {
+                            const FemApplyArgs &a, void *workspace, int blocks_per_cu,
+                            int variant, hipStream_t stream, hipEvent_t ev_start,
+                            hipEvent_t ev_stop) {
   if (a.E <= 0 || a.n_members <= 0) return hipSuccess;
+  // variant 2: S as scalar operands; 0 and 1: S in LDS (measured faster on
+  // most shapes; the tuner picks per shape)
+  const bool sreg = variant == 2;
+  if (sreg && !workspace) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
+  if (sreg) {
+    const int NIP = (NI + 1) & ~1;
+    const int total = NC * NJ * NIP;
+    const unsigned g = (unsigned)std::min(64, (total + 255) / 256);
+    if (f64)
+      hipLaunchKernelGGL(apply_pack_kernel<double>, dim3(g), dim3(256), 0, stream, a,
+                         (double *)workspace, NI, NJ, NC, NIP);
+    else
+      hipLaunchKernelGGL(apply_pack_kernel<float>, dim3(g), dim3(256), 0, stream, a,
+                         (float *)workspace, NI, NJ, NC, NIP);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
   e = hipErrorInvalidValue;
 #define BES_APPLY_DISPATCH(ni, nj, nc, nx, dg)                                              \
   if (NI == ni && NJ == nj && NC == nc && NX == nx && diag == dg)                           \
-    e = f64 ? launch_apply_shape<double, ni, nj, nc, nx, dg>(a, blocks_per_cu, stream)      \
-            : launch_apply_shape<float, ni, nj, nc, nx, dg>(a, blocks_per_cu, stream);
+    e = f64 ? launch_apply_shape<double, ni, nj, nc, nx, dg>(a, (const double *)workspace,  \
+                                                             blocks_per_cu, sreg, stream)   \
+            : launch_apply_shape<float, ni, nj, nc, nx, dg>(a, (const float *)workspace,    \
+                                                            blocks_per_cu, sreg, stream);
   BES_FEM_APPLY_SHAPES(BES_APPLY_DISPATCH)
 #undef BES_APPLY_DISPATCH
   if (e != hipSuccess) return e;

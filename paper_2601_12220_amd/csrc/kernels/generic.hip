@@ -27,10 +27,10 @@ __device__ __forceinline__ T bes_expr(int, T, T) {
 
 #include "generic_body.inc"
 
-template <typename T>
+template <typename T, bool NARROW>
 __global__ void __launch_bounds__(256) generic_kernel(const GenEinsum *__restrict__ G,
                                                       const GenPtrs P, int64_t tiles_per_slot) {
-  generic_block<T>(G, P, tiles_per_slot);
+  generic_block<T, NARROW>(G, P, tiles_per_slot);
 }
 
 // Block row blockIdx.y is the einsum of the persistent table.
@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(256) zero_split_one(const GenEinsum *__restric
   zero_slots<T>(*G, P);
 }
 
-template <typename T>
+template <typename T, bool NARROW>
 __global__ void __launch_bounds__(256) persistent_kernel(const GenEinsum *__restrict__ table,
                                                          const GenPtrs *__restrict__ ptrs,
                                                          const GenItem *__restrict__ items,
@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(256) persistent_kernel(const GenEinsum *__rest
     __syncthreads();
     if (it >= n_items) break;
     const GenItem w = items[it];
-    gen_tile<T>(&table[w.einsum], &ptrs[w.einsum], w.slot, w.first, w.count, w.chunk);
+    gen_tile<T, NARROW>(&table[w.einsum], &ptrs[w.einsum], w.slot, w.first, w.count, w.chunk);
   }
   if (threadIdx.x == 0) {
     __threadfence();
@@ -107,16 +107,20 @@ hipError_t launch_generic(bool f64, const GenEinsum *dev, const GenEinsum &host,
       hipLaunchKernelGGL(zero_split_one<float>, dim3(g), dim3(256), 0, stream, dev, ptrs);
   }
   dim3 grid((unsigned)blocks), block(256);
-  if (f64)
-    hipLaunchKernelGGL(generic_kernel<double>, grid, block, 0, stream, dev, ptrs, tiles);
+  if (f64 && host.narrow)
+    hipLaunchKernelGGL((generic_kernel<double, true>), grid, block, 0, stream, dev, ptrs, tiles);
+  else if (f64)
+    hipLaunchKernelGGL((generic_kernel<double, false>), grid, block, 0, stream, dev, ptrs, tiles);
+  else if (host.narrow)
+    hipLaunchKernelGGL((generic_kernel<float, true>), grid, block, 0, stream, dev, ptrs, tiles);
   else
-    hipLaunchKernelGGL(generic_kernel<float>, grid, block, 0, stream, dev, ptrs, tiles);
+    hipLaunchKernelGGL((generic_kernel<float, false>), grid, block, 0, stream, dev, ptrs, tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_persistent(bool f64, const GenEinsum *table, const GenPtrs *ptrs,
                              const GenItem *items, int n_items, unsigned *counters, int grid,
-                             hipStream_t stream, int n_einsums, bool any_split) {
+                             hipStream_t stream, int n_einsums, bool any_split, bool narrow) {
   if (n_items <= 0) return hipSuccess;
   if (grid < 1) grid = 1;
   if (any_split) {
@@ -127,12 +131,18 @@ hipError_t launch_persistent(bool f64, const GenEinsum *table, const GenPtrs *pt
       hipLaunchKernelGGL(zero_split_outputs<float>, dim3(64, n_einsums), dim3(256), 0, stream,
                          table, ptrs);
   }
-  if (f64)
-    hipLaunchKernelGGL(persistent_kernel<double>, dim3(grid), dim3(256), 0, stream, table, ptrs,
-                       items, n_items, counters);
+  if (f64 && narrow)
+    hipLaunchKernelGGL((persistent_kernel<double, true>), dim3(grid), dim3(256), 0, stream,
+                       table, ptrs, items, n_items, counters);
+  else if (f64)
+    hipLaunchKernelGGL((persistent_kernel<double, false>), dim3(grid), dim3(256), 0, stream,
+                       table, ptrs, items, n_items, counters);
+  else if (narrow)
+    hipLaunchKernelGGL((persistent_kernel<float, true>), dim3(grid), dim3(256), 0, stream,
+                       table, ptrs, items, n_items, counters);
   else
-    hipLaunchKernelGGL(persistent_kernel<float>, dim3(grid), dim3(256), 0, stream, table, ptrs,
-                       items, n_items, counters);
+    hipLaunchKernelGGL((persistent_kernel<float, false>), dim3(grid), dim3(256), 0, stream,
+                       table, ptrs, items, n_items, counters);
   return hipGetLastError();
 }
 

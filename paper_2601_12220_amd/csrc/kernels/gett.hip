@@ -11,9 +11,10 @@
 // the host), the affine map is applied in registers on the way to LDS, and
 // out-of-range elements of ragged edge tiles enter as exact zeros.
 //
-// Tiling: 64 x 64 output tile per block of four waves (2 x 2, 32 x 32 each as
-// 2 x 2 MFMA tiles of 16 x 16), K staged 16 deep through double-buffered LDS
-// with register prefetch of the next stage.  FP64 runs v_mfma_f64_16x16x4f64,
+// Tiling: an output tile per block of four waves (64 x 64, or a skinny
+// 16 x 128, 32 x 128, 128 x 32 or 128 x 16 when the output has few rows or
+// columns), each wave a grid of 16 x 16 MFMA tiles, K staged 8 or 16 deep
+// through double-buffered LDS with register prefetch of the next stage.  FP64 runs v_mfma_f64_16x16x4f64,
 // FP32 v_mfma_f32_16x16x4f32.  Each operand's tile is read along whichever
 // of its two groups is contiguous in memory (host flag), so that neighbouring
 // lanes read neighbouring addresses.
@@ -27,8 +28,8 @@ namespace bes {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
 constexpr int kThreads = 256;
+constexpr int kBM0 = 64, kBN0 = 64, kBK0 = 16;   // the square tile shape
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -61,15 +62,16 @@ struct MatrixCore<float> {
 // Gather of one K stage of a 64 x 16 operand tile into registers (4 values
 // per thread).  `fast` = the tile is read along its 16-wide K side (A) or
 // along its 64-wide side (B): the host picks the side with unit stride.
+template <int E>
 struct Stage {
-  int64_t o[4];      // element offsets (row + column), or -1 when out of range
+  int64_t o[E];      // element offsets (row + column), or -1 when out of range
 };
 
-template <typename T>
-__device__ __forceinline__ void gather(const T *__restrict__ base, const Stage &s, T alpha, T beta,
-                                       T (&v)[4]) {
+template <typename T, int E>
+__device__ __forceinline__ void gather(const T *__restrict__ base, const Stage<E> &s, T alpha,
+                                       T beta, T (&v)[E]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = s.o[q] >= 0 ? fma(alpha, base[s.o[q]], beta) : (T)0;
+  for (int q = 0; q < E; ++q) v[q] = s.o[q] >= 0 ? fma(alpha, base[s.o[q]], beta) : (T)0;
 }
 
 // Zero the overwritten outputs of a split-K launch (its partial tiles add
@@ -86,15 +88,29 @@ __global__ void __launch_bounds__(kThreads) gett_zero_kernel(const GettArgs a) {
   }
 }
 
-template <typename T>
+// Tile shapes: BM x BN outputs per block of four waves laid out WM x WN,
+// each wave 16 TI x 16 TJ; K staged BK deep.  The skinny shapes serve
+// contractions with few rows or columns (TCCG-like cases often have one
+// small free side), where a square tile would be mostly padding.
+template <int BM_, int BN_, int BK_, int WM_>
+struct Tile {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = 4 / WM_;
+  static constexpr int TI = BM / (16 * WM), TJ = BN / (16 * WN);
+  static constexpr int EA = BM * BK / kThreads, EB = BN * BK / kThreads;   // per thread
+  static_assert(TI >= 1 && TJ >= 1 && EA >= 1 && EB >= 1, "tile shape");
+};
+
+template <typename T, typename TL>
 __global__ void __launch_bounds__(kThreads) gett_kernel(const GettArgs a, int tiles_m,
                                                         int tiles_n) {
   typedef MatrixCore<T> MC;
+  constexpr int BM = TL::BM, BN = TL::BN, BK = TL::BK, TI = TL::TI, TJ = TL::TJ;
+  constexpr int EA = TL::EA, EB = TL::EB;
   constexpr int LDA = BM + 1, LDB = BN + 1;
   __shared__ T As[2][BK * LDA];
   __shared__ T Bs[2][BK * LDB];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / TL::WN, wn = wave - wm * TL::WN;
   // block = (slot, tile, K range), K range fastest; tiles are dealt so that
   // each of the 8 XCDs gets a contiguous band (its L2 holds the shared panels)
   const int tiles = tiles_m * tiles_n;
@@ -109,11 +125,11 @@ __global__ void __launch_bounds__(kThreads) gett_kernel(const GettArgs a, int ti
   const int64_t *__restrict__ tab = a.tab;
   const int64_t M = a.M, N = a.N, K = a.K;
 
-  typename MC::acc_t acc[2][2];
+  typename MC::acc_t acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = typename MC::acc_t{0, 0, 0, 0};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = typename MC::acc_t{0, 0, 0, 0};
 
   // K stages [kb, ke) of every member of the slot belong to this block
   const int64_t ktot = (K + BK - 1) / BK;
@@ -121,72 +137,76 @@ __global__ void __launch_bounds__(kThreads) gett_kernel(const GettArgs a, int ti
   const int64_t kt = ke - kb;
   const int64_t steps = kt * (S.m1 - S.m0);
 
-  // Offsets of this thread's 4 A values and 4 B values at K stage k0.
-  auto stage_a = [&](const GettMember &mb, int64_t k0, Stage &s) {
-    const int64_t *rowA = tab + mb.rowA, *colA = tab + mb.colA;
-    if (mb.a_kfast) {            // kk = t % 16, m = t / 16 + 16 q
-      const int64_t k = k0 + (t & 15);
-      const int64_t ck = k < K ? colA[k] : 0;
+  // Element (row, kk) of this thread's q-th A value: along K (k-fast:
+  // kk = t % BK, row = t / BK + (256 / BK) q) or along M (m-fast:
+  // row = t % BM, kk = t / BM + (256 / BM) q); B likewise with N.
+  auto a_row = [&](const GettMember &mb, int q) {
+    return mb.a_kfast ? t / BK + (kThreads / BK) * q : t % BM;
+  };
+  auto a_kk = [&](const GettMember &mb, int q) {
+    return mb.a_kfast ? t % BK : t / BM + (kThreads / BM) * q;
+  };
+  auto b_col = [&](const GettMember &mb, int q) {
+    return mb.b_nfast ? t % BN : t / BK + (kThreads / BK) * q;
+  };
+  auto b_kk = [&](const GettMember &mb, int q) {
+    return mb.b_nfast ? t / BN + (kThreads / BN) * q : t % BK;
+  };
+  // The M offsets of A's rows and the N offsets of B's columns that this
+  // thread gathers do not change along K: looked up once per member (-1:
+  // outside the output).  Only the K offsets are looked up per stage.
+  int64_t rowoff[EA], coloff[EB];
+  int cur = -1;
+  auto member_offsets = [&](int mi) {
+    if (mi == cur) return;
+    cur = mi;
+    const GettMember &mb = a.mem[mi];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t m = m0 + (t >> 4) + 16 * q;
-        s.o[q] = (k < K && m < M) ? rowA[m] + ck : -1;
-      }
-    } else {                     // m = t % 64, kk = t / 64 + 4 q
-      const int64_t m = m0 + (t & 63);
-      const int64_t rm = m < M ? rowA[m] : 0;
+    for (int q = 0; q < EA; ++q) {
+      const int64_t m = m0 + a_row(mb, q);
+      rowoff[q] = m < M ? tab[mb.rowA + m] : -1;
+    }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t k = k0 + (t >> 6) + 4 * q;
-        s.o[q] = (k < K && m < M) ? rm + colA[k] : -1;
-      }
+    for (int q = 0; q < EB; ++q) {
+      const int64_t n = n0 + b_col(mb, q);
+      coloff[q] = n < N ? tab[mb.colB + n] : -1;
     }
   };
-  auto stage_b = [&](const GettMember &mb, int64_t k0, Stage &s) {
-    const int64_t *rowB = tab + mb.rowB, *colB = tab + mb.colB;
-    if (mb.b_nfast) {            // n = t % 64, kk = t / 64 + 4 q
-      const int64_t n = n0 + (t & 63);
-      const int64_t cn = n < N ? colB[n] : 0;
+  auto stage_a = [&](const GettMember &mb, int64_t k0, Stage<EA> &s) {
+    const int64_t *colA = tab + mb.colA;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t k = k0 + (t >> 6) + 4 * q;
-        s.o[q] = (k < K && n < N) ? rowB[k] + cn : -1;
-      }
-    } else {                     // kk = t % 16, n = t / 16 + 16 q
-      const int64_t k = k0 + (t & 15);
-      const int64_t rk = k < K ? rowB[k] : 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t n = n0 + (t >> 4) + 16 * q;
-        s.o[q] = (k < K && n < N) ? rk + colB[n] : -1;
-      }
+    for (int q = 0; q < EA; ++q) {
+      const int64_t k = k0 + a_kk(mb, q);
+      s.o[q] = (k < K && rowoff[q] >= 0) ? rowoff[q] + colA[k] : -1;
     }
   };
-  auto put_a = [&](T *__restrict__ dst, const GettMember &mb, const T (&v)[4]) {
+  auto stage_b = [&](const GettMember &mb, int64_t k0, Stage<EB> &s) {
+    const int64_t *rowB = tab + mb.rowB;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = mb.a_kfast ? (t >> 4) + 16 * q : (t & 63);
-      const int kk = mb.a_kfast ? (t & 15) : (t >> 6) + 4 * q;
-      dst[kk * LDA + m] = v[q];
+    for (int q = 0; q < EB; ++q) {
+      const int64_t k = k0 + b_kk(mb, q);
+      s.o[q] = (k < K && coloff[q] >= 0) ? rowB[k] + coloff[q] : -1;
     }
   };
-  auto put_b = [&](T *__restrict__ dst, const GettMember &mb, const T (&v)[4]) {
+  auto put_a = [&](T *__restrict__ dst, const GettMember &mb, const T (&v)[EA]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int n = mb.b_nfast ? (t & 63) : (t >> 4) + 16 * q;
-      const int kk = mb.b_nfast ? (t >> 6) + 4 * q : (t & 15);
-      dst[kk * LDB + n] = v[q];
-    }
+    for (int q = 0; q < EA; ++q) dst[a_kk(mb, q) * LDA + a_row(mb, q)] = v[q];
+  };
+  auto put_b = [&](T *__restrict__ dst, const GettMember &mb, const T (&v)[EB]) {
+#pragma unroll
+    for (int q = 0; q < EB; ++q) dst[b_kk(mb, q) * LDB + b_col(mb, q)] = v[q];
   };
 
-  T va[4], vb[4];
+  T va[EA], vb[EB];
   if (steps > 0) {
+    member_offsets(S.m0);
     const GettMember &mb = a.mem[S.m0];
-    Stage sa, sb;
+    Stage<EA> sa;
+    Stage<EB> sb;
     stage_a(mb, kb * BK, sa);
     stage_b(mb, kb * BK, sb);
-    gather<T>((const T *)mb.A, sa, (T)mb.a_alpha, (T)mb.a_beta, va);
-    gather<T>((const T *)mb.B, sb, (T)mb.b_alpha, (T)mb.b_beta, vb);
+    gather<T, EA>((const T *)mb.A, sa, (T)mb.a_alpha, (T)mb.a_beta, va);
+    gather<T, EB>((const T *)mb.B, sb, (T)mb.b_alpha, (T)mb.b_beta, vb);
     put_a(As[0], mb, va);
     put_b(Bs[0], mb, vb);
   }
@@ -198,27 +218,29 @@ __global__ void __launch_bounds__(kThreads) gett_kernel(const GettArgs a, int ti
     if (more) {
       nm = S.m0 + (int)((s + 1) / kt);
       const int64_t nk0 = (kb + (s + 1) % kt) * BK;
+      member_offsets(nm);
       const GettMember &mb = a.mem[nm];
-      Stage sa, sb;
+      Stage<EA> sa;
+      Stage<EB> sb;
       stage_a(mb, nk0, sa);
       stage_b(mb, nk0, sb);
-      gather<T>((const T *)mb.A, sa, (T)mb.a_alpha, (T)mb.a_beta, va);
-      gather<T>((const T *)mb.B, sb, (T)mb.b_alpha, (T)mb.b_beta, vb);
+      gather<T, EA>((const T *)mb.A, sa, (T)mb.a_alpha, (T)mb.a_beta, va);
+      gather<T, EB>((const T *)mb.B, sb, (T)mb.b_alpha, (T)mb.b_beta, vb);
     }
     const T *__restrict__ as = As[buf];
     const T *__restrict__ bs = Bs[buf];
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      T fa[2], fb[2];
+      T fa[TI], fb[TJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) fa[i] = as[kr * LDA + wm * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < TI; ++i) fa[i] = as[kr * LDA + (wm * TI + i) * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fb[j] = bs[kr * LDB + wn * 32 + j * 16 + (lane & 15)];
+      for (int j = 0; j < TJ; ++j) fb[j] = bs[kr * LDB + (wn * TJ + j) * 16 + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = MC::mma(fa[i], fb[j], acc[i][j]);
+        for (int j = 0; j < TJ; ++j) acc[i][j] = MC::mma(fa[i], fb[j], acc[i][j]);
     }
     if (more) {
       put_a(As[buf ^ 1], a.mem[nm], va);
@@ -229,15 +251,15 @@ __global__ void __launch_bounds__(kThreads) gett_kernel(const GettArgs a, int ti
   T *__restrict__ C = (T *)S.C;
   const int64_t *rowC = tab + S.rowC, *colC = tab + S.colC;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int64_t n = n0 + wn * 32 + j * 16 + (lane & 15);
+  for (int j = 0; j < TJ; ++j) {
+    const int64_t n = n0 + (wn * TJ + j) * 16 + (lane & 15);
     if (n >= N) continue;
     const int64_t cn = colC[n];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t m = m0 + wm * 32 + i * 16 + MC::row(v, lane);
+        const int64_t m = m0 + (wm * TI + i) * 16 + MC::row(v, lane);
         if (m >= M) continue;
         T *p = C + rowC[m] + cn;
         if (a.ksplit > 1) atomicAdd(p, acc[i][j][v]);   // into zeroed or caller's C
@@ -246,19 +268,19 @@ __global__ void __launch_bounds__(kThreads) gett_kernel(const GettArgs a, int ti
   }
 }
 
-}  // namespace
-
-hipError_t launch_gett(bool f64, const GettArgs &args, int ksplit, hipStream_t stream) {
-  if (args.M <= 0 || args.N <= 0 || args.n_slots <= 0) return hipSuccess;
+template <typename T, typename TL>
+hipError_t launch_tile(const GettArgs &args, int ksplit, hipStream_t stream) {
   GettArgs a = args;
-  const int64_t tm = (a.M + BM - 1) / BM, tn = (a.N + BN - 1) / BN;
+  const int64_t tm = (a.M + TL::BM - 1) / TL::BM, tn = (a.N + TL::BN - 1) / TL::BN;
   const int64_t base = tm * tn * a.n_slots;
-  const int64_t ktot = (a.K + BK - 1) / BK;
+  const int64_t ktot = (a.K + TL::BK - 1) / TL::BK;
   // Split K when the output tiles alone cannot fill the chip: enough ranges
-  // for about four blocks per compute unit, each at least four K stages.
+  // for about two blocks per compute unit, each at least sixteen K stages
+  // (every range adds its partial tile atomically, and many ranges per
+  // output contend on the same addresses).
   if (ksplit <= 0) {
-    const int64_t want = (4 * (int64_t)device_cu_count() + base - 1) / base;
-    ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, ktot / 4, 256}));
+    const int64_t want = (2 * (int64_t)device_cu_count() + base - 1) / base;
+    ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, ktot / 16, 64}));
   }
   a.ksplit = std::max(1, std::min<int>(ksplit, (int)std::max<int64_t>(ktot, 1)));
   const int64_t blocks = base * a.ksplit;
@@ -266,18 +288,34 @@ hipError_t launch_gett(bool f64, const GettArgs &args, int ksplit, hipStream_t s
   if (a.ksplit > 1) {
     const int64_t n = a.M * a.N * a.n_slots;
     const unsigned g = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 8192);
-    if (f64)
-      hipLaunchKernelGGL(gett_zero_kernel<double>, dim3(g), dim3(kThreads), 0, stream, a);
-    else
-      hipLaunchKernelGGL(gett_zero_kernel<float>, dim3(g), dim3(kThreads), 0, stream, a);
+    hipLaunchKernelGGL(gett_zero_kernel<T>, dim3(g), dim3(kThreads), 0, stream, a);
   }
-  if (f64)
-    hipLaunchKernelGGL(gett_kernel<double>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
-                       a, (int)tm, (int)tn);
-  else
-    hipLaunchKernelGGL(gett_kernel<float>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
-                       a, (int)tm, (int)tn);
+  hipLaunchKernelGGL((gett_kernel<T, TL>), dim3((unsigned)blocks), dim3(kThreads), 0, stream, a,
+                     (int)tm, (int)tn);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_shape(const GettArgs &a, int shape, int ksplit, hipStream_t stream) {
+  switch (shape) {
+    case 1: return launch_tile<T, Tile<16, 128, 16, 1>>(a, ksplit, stream);
+    case 2: return launch_tile<T, Tile<32, 128, 8, 1>>(a, ksplit, stream);
+    case 3: return launch_tile<T, Tile<128, 32, 8, 4>>(a, ksplit, stream);
+    case 4: return launch_tile<T, Tile<128, 16, 16, 4>>(a, ksplit, stream);
+    default: return launch_tile<T, Tile<kBM0, kBN0, kBK0, 2>>(a, ksplit, stream);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gett(bool f64, const GettArgs &a, int shape, int ksplit,
+                       hipStream_t stream) {
+  if (a.M <= 0 || a.N <= 0 || a.n_slots <= 0) return hipSuccess;
+  // shape 0: by the output's extents -- skinny tiles for few rows or columns
+  if (shape <= 0)
+    shape = a.M <= 16 ? 1 : a.M <= 32 ? 2 : a.N <= 16 ? 4 : a.N <= 32 ? 3 : 5;
+  return f64 ? launch_shape<double>(a, shape, ksplit, stream)
+             : launch_shape<float>(a, shape, ksplit, stream);
 }
 
 }  // namespace bes

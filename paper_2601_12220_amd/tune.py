@@ -34,17 +34,18 @@ def candidates(template_id: int) -> List[Tuple[int, ...]]:
     Generic:    p[0] = outputs per tile, p[1] = lanes per output, p[2] = chunks
                 of the shared contracted space (their sums add into the output).
     MFMA:       the single 128 x 128 tile shape the template implements.
-    GETT:       64 x 64 tiles; p[2] = K ranges per output tile."""
+    GETT:       p[2] = K ranges per output tile, p[3] = tile shape."""
     if template_id == T_FEM_STREAM:
-        return [(T_FEM_STREAM, 64, b, v) for v in (0, 2, 1) for b in (8, 16, 32, 64)]
+        return [(T_FEM_STREAM, 64, b, v) for v in (0, 2, 1) for b in (4, 8, 16, 32, 64)]
     if template_id == T_GENERIC:
         # p[2]: chunks of the shared contracted space per output (1: none)
         return ([(T_GENERIC, tile, lanes, 1) for tile in (64, 256, 1024) for lanes in (1, 4, 16, 64)]
                 + [(T_GENERIC, 256, lanes, split) for lanes in (16, 64) for split in (8, 64)])
     if template_id == T_MFMA:
         return [(T_MFMA, 128, 128)]
-    if template_id == T_GETT:   # p[2]: K ranges per output tile (0: launcher's choice)
-        return [(T_GETT, 64, 64, ks) for ks in (0, 1, 4, 16, 64)]
+    if template_id == T_GETT:   # p[2]: K ranges per tile (0: launcher's), p[3]: tile shape
+        return ([(T_GETT, 64, 64, ks, 0) for ks in (0, 1, 4, 16, 64)] +
+                [(T_GETT, 64, 64, 0, sh) for sh in (1, 2, 3, 4, 5)])
     return []
 
 
@@ -57,44 +58,64 @@ class TuneResult:
 
 
 def time_launches(launch, stream, reps: int, warmup: int) -> float:
-    """Mean seconds per call of ``launch()`` between HIP events recorded on
-    ``stream`` (a torch stream), after ``warmup`` untimed calls."""
+    """Mean seconds per call of ``launch(handle)`` on ``stream`` (a torch
+    stream): after ``warmup`` eager calls (which also make every allocation
+    a first launch needs), ``reps`` calls are captured in one HIP graph and
+    the graph is replayed between HIP events, so host launch overhead does
+    not blur the differences between candidates of short kernels."""
     import torch
+    h = int(stream.cuda_stream)
     for _ in range(warmup):
-        launch()
+        launch(h)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        hh = int(torch.cuda.current_stream().cuda_stream)
+        for _ in range(reps):
+            launch(hh)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(reps):
-        launch()
-    end.record(stream)
+    with torch.cuda.stream(stream):
+        g.replay()
+        start.record(stream)
+        g.replay()
+        end.record(stream)
     end.synchronize()
+    del g
     return start.elapsed_time(end) * 1e-3 / reps
 
 
 def tune(ctx, plan, buffers: Dict[str, object], outputs: Sequence[object], stream=None,
          reps: int = 20, warmup: int = 3, arch: str = "gfx950",
-         record: bool = True) -> Optional[TuneResult]:
+         record: bool = True, rounds: int = 1) -> Optional[TuneResult]:
     """Time every candidate of the plan's current template on ``buffers`` /
     ``outputs`` (device tensors), install the fastest in the plan and, with
     ``record``, append it to the context's database.  Returns None when the
     template has nothing to tune."""
     import torch
     stream = stream if stream is not None else torch.cuda.current_stream()
-    handle = int(stream.cuda_stream)
+    if stream == torch.cuda.default_stream():
+        # graphs are not captured on the legacy default stream: time on a
+        # side stream, after everything queued so far has finished
+        torch.cuda.synchronize()
+        stream = torch.cuda.Stream()
     cands = candidates(plan.config.template_id)
     if not cands:
         return None
     src = plan.src_ptrs(buffers)
     outs = [o.data_ptr() for o in outputs]
     timings: Dict[Tuple[int, ...], float] = {}
-    for c in cands:
-        try:
-            plan.set_config(*c)
-        except capi.BesError:
-            continue                      # the template rejects this shape
-        timings[c] = time_launches(lambda: plan.launch_ptrs(src, outs, handle), stream, reps,
-                                   warmup)
+    # every candidate is timed in `rounds` interleaved rounds and keeps its
+    # best round, so that a transient slowdown of the device during one
+    # candidate's turn does not decide the choice
+    for _ in range(rounds):
+        for c in cands:
+            try:
+                plan.set_config(*c)
+            except capi.BesError:
+                continue                      # the template rejects this shape
+            t = time_launches(lambda h: plan.launch_ptrs(src, outs, h), stream, reps, warmup)
+            timings[c] = min(t, timings.get(c, t))
     if not timings:
         return None
     best = min(timings, key=timings.get)

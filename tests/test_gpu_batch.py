@@ -167,3 +167,25 @@ def test_benched_256_batch_matches_oracle_and_plain(benched_batch):
             assert rel_fro(got_p, refs[k][m]) <= TOL["float32"], (k, w.notation, m)
             assert rel_fro(got_b, got_p) <= TOL["float32"], (k, m)
     _say(f"[batch256] worst relative Frobenius error vs oracle {worst:.3e}")
+
+
+def test_bind_once_then_replay(batch_setup):
+    """bes_batch_bind + bes_batch_replay: pointers bound once, several
+    replays, each checked against the oracle; a replay before any bind is
+    refused."""
+    ws, ctx, plans, bufs, refs = batch_setup
+    batch = Batch(ctx, plans[:10])
+    with pytest.raises(capi.BesError):
+        batch.replay(0)
+    outs = [_nan_outputs(w) for w in ws[:10]]
+    batch.bind_ptrs([p.src_ptrs(b) for p, b in zip(plans[:10], bufs[:10])],
+                    [[o.data_ptr() for o in os_] for os_ in outs], 0)
+    for rep in range(3):
+        for os_ in outs:
+            for o in os_:
+                o.fill_(float("nan"))
+        batch.replay(0)
+        torch.cuda.synchronize()
+        for k in range(10):
+            for m in range(ws[k].b):
+                assert rel_fro(outs[k][m].double().cpu().numpy(), refs[k][m]) <= TOL["float32"]

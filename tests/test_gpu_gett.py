@@ -113,3 +113,16 @@ def test_gett_full_size_stand_in_sampled(ctx, case):
     pos, ref = oracle_sampled(w, n_samples=1024)
     got = outs[0].reshape(-1)[torch.as_tensor(pos, device="cuda")].double().cpu().numpy()
     assert rel_fro(got, ref[0]) <= TOL["float64"]
+
+
+@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("ksplit", [1, 3])
+def test_gett_every_tile_shape(ctx, shape, ksplit):
+    # each tile shape on ragged operands (rows and columns not multiples of
+    # the tile), with and without a K split
+    for notation, shapes in (("abc,cd->adb", {"A": (21, 7, 40), "B": (40, 150)}),
+                             ("kji,kl->lij", {"A": (37, 13, 11), "B": (37, 290)})):
+        w = _workload(notation, [["A", "B"]], shapes, affine=("A", "B"))
+        plan = ctx.register(w.notation, w.table, w.operands)
+        plan.set_config(T_GETT, 64, 64, ksplit, shape)
+        _check(plan, w, TOL["float64"])
