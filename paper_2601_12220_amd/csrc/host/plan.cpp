@@ -119,6 +119,19 @@ void analyse_fem_grad(Plan &p) {
       if (X.size() != 2) continue;
       int j = X[0] == E ? X[1] : X[0];
       if (!(contains(S, j) && !in_out(j) && !contains(Y, j))) continue;
+      // the extents this choice gives the kernel must be compiled
+      int rr = -1, xx = -1, ii = -1;
+      for (int c : Y) {
+        if (c == E) continue;
+        if (contains(S, c) && !in_out(c)) rr = c;
+        else if (in_out(c) && !contains(S, c)) xx = c;
+      }
+      for (int c : S)
+        if (c != rr && c != j) ii = c;
+      if (rr >= 0 && ii >= 0 && S.size() == 3 &&
+          !fem_shape_compiled(p.spec.dtype == BES_FLOAT64, (int)e.extent[ii], (int)e.extent[j],
+                              (int)e.extent[rr], xx >= 0 ? (int)e.extent[xx] : 1))
+        continue;
       std::vector<int> distinct;
       for (int m = 0; m < e.b; ++m) {
         int a = e.arg(m, with_e[k]);

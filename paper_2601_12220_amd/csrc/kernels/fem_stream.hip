@@ -47,42 +47,35 @@ constexpr int kTile = 64;      // elements per wave tile = lanes per wave
 constexpr int kPitch = kTile + 1;
 constexpr int kMaxRow = 12;    // staged G row width (TET: 4 x 3 vertex coords)
 
-// FP64 sin (shift 0) or cos (shift 1) for |x| < 2^20: Cody-Waite reduction
-// r = x - n pi/2 with pi/2 split in three parts (the first two with 33
-// significant bits, so n times them is exact for |n| < 2^20), then the Taylor
-// series of sin and cos on [-pi/4, pi/4] to degrees 19 and 20 (truncation
-// below 1e-19), chosen and signed by the quadrant n mod 4: about 30 FP64
-// operations.  Callers check the range for the whole wave first.
+// FP64 sin (shift 0) or cos (shift 1) for |x| < 2^20 with one polynomial:
+// Cody-Waite reduction by pi, x = (k + shift/2) pi + r with |r| <= pi/2 (pi
+// split in three parts, the first two with 33 significant bits, so that
+// (k + 1/2) times them is exact for |k| < 2^19), then
+// op(x) = (-1)^(k + shift) sin(r), sin(r) by its Taylor series to degree 21
+// (truncation below 2e-18 on |r| <= pi/2): about 22 operations, every one
+// of them on every lane (no data-dependent choice between two series).
+// Callers check the range for the whole wave first.
 __device__ __forceinline__ double sincos_small(double x, int shift) {
-  const double n = rint(x * 0x1.45f306dc9c883p-1);   // x * 2/pi
-  double r = fma(-n, 0x1.921fb54400000p+0, x);
-  r = fma(-n, 0x1.0b4611a600000p-34, r);
-  r = fma(-n, 0x1.3198a2e037073p-69, r);
+  const double h = 0.5 * shift;
+  const double k = rint(fma(x, 0x1.45f306dc9c883p-2, -h));   // x / pi - h
+  const double m = k + h;
+  double r = fma(-m, 0x1.921fb54400000p+1, x);
+  r = fma(-m, 0x1.0b4611a600000p-33, r);
+  r = fma(-m, 0x1.3198a2e037073p-68, r);
   const double r2 = r * r;
-  double ps = -1.0 / 121645100408832000.0;           // -1/19!
-  ps = fma(ps, r2, 1.0 / 355687428096000.0);          //  1/17!
-  ps = fma(ps, r2, -1.0 / 1307674368000.0);           // -1/15!
-  ps = fma(ps, r2, 1.0 / 6227020800.0);               //  1/13!
-  ps = fma(ps, r2, -1.0 / 39916800.0);                // -1/11!
-  ps = fma(ps, r2, 1.0 / 362880.0);                   //  1/9!
-  ps = fma(ps, r2, -1.0 / 5040.0);                    // -1/7!
-  ps = fma(ps, r2, 1.0 / 120.0);                      //  1/5!
-  ps = fma(ps, r2, -1.0 / 6.0);                       // -1/3!
-  const double sr = fma(ps * r2, r, r);
-  double pc = 1.0 / 2432902008176640000.0;            //  1/20!
-  pc = fma(pc, r2, -1.0 / 6402373705728000.0);        // -1/18!
-  pc = fma(pc, r2, 1.0 / 20922789888000.0);           //  1/16!
-  pc = fma(pc, r2, -1.0 / 87178291200.0);             // -1/14!
-  pc = fma(pc, r2, 1.0 / 479001600.0);                //  1/12!
-  pc = fma(pc, r2, -1.0 / 3628800.0);                 // -1/10!
-  pc = fma(pc, r2, 1.0 / 40320.0);                    //  1/8!
-  pc = fma(pc, r2, -1.0 / 720.0);                     // -1/6!
-  pc = fma(pc, r2, 1.0 / 24.0);                       //  1/4!
-  pc = fma(pc, r2, -0.5);                             // -1/2!
-  const double cr = fma(pc, r2, 1.0);
-  const int q = ((int)n + shift) & 3;
-  const double v = (q & 1) ? cr : sr;
-  return (q & 2) ? -v : v;
+  double p = 1.0 / 51090942171709440000.0;            //  1/21!
+  p = fma(p, r2, -1.0 / 121645100408832000.0);        // -1/19!
+  p = fma(p, r2, 1.0 / 355687428096000.0);            //  1/17!
+  p = fma(p, r2, -1.0 / 1307674368000.0);             // -1/15!
+  p = fma(p, r2, 1.0 / 6227020800.0);                 //  1/13!
+  p = fma(p, r2, -1.0 / 39916800.0);                  // -1/11!
+  p = fma(p, r2, 1.0 / 362880.0);                     //  1/9!
+  p = fma(p, r2, -1.0 / 5040.0);                      // -1/7!
+  p = fma(p, r2, 1.0 / 120.0);                        //  1/5!
+  p = fma(p, r2, -1.0 / 6.0);                         // -1/3!
+  const double sr = fma(r2 * p, r, r);
+  const unsigned odd = (unsigned)((int)k + shift) & 1u;
+  return __hiloint2double(__double2hiint(sr) ^ (int)(odd << 31), __double2loint(sr));
 }
 
 template <typename T>
@@ -165,14 +158,15 @@ __device__ __forceinline__ void stage_rows_rolled(T *__restrict__ X, const FemSr
 // Tetrahedron Jacobian of this lane's element from its staged vertex row
 // (components vertex * 3 + coordinate): J[x][r] = V[r+1][x] - V[0][x]; the
 // kernel's (x, r) may be the operand's (r, x).  NX = NR = 3 on this path.
-template <typename T, int NX, int NR>
+// Staged rows are P apart.
+template <typename T, int NX, int NR, int P = kPitch>
 __device__ __forceinline__ void tet_from_lds(const T *__restrict__ X, int lane, bool swapped,
                                              T (&g)[NX][NR]) {
   T v[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[k][c] = X[(k * 3 + c) * kPitch + lane];
+    for (int c = 0; c < 3; ++c) v[k][c] = X[(k * 3 + c) * P + lane];
 #pragma unroll
   for (int x = 0; x < NX; ++x)
 #pragma unroll
@@ -189,17 +183,17 @@ constexpr bool kTetCapable = NX == 3 && NR == 3;
 // G components of member descriptor s from the staged row in X:
 // views read (off0 + x*sx + r*sr) of the row, tetrahedra the 12 vertex
 // coordinates.
-template <typename T, int NX, int NR>
+template <typename T, int NX, int NR, int P = kPitch>
 __device__ __forceinline__ void g_from_row(const T *__restrict__ X, const FemSrc &s, int lane,
                                            T (&g)[NX][NR]) {
   if (kTetCapable<NX, NR> && s.kind == FEM_SRC_TET) {
-    if constexpr (kTetCapable<NX, NR>) tet_from_lds<T, NX, NR>(X, lane, s.s1[0] != 0, g);
+    if constexpr (kTetCapable<NX, NR>) tet_from_lds<T, NX, NR, P>(X, lane, s.s1[0] != 0, g);
   } else {
     const int off = (int)s.off0, sx = (int)s.s0[1], sr = (int)s.s0[2];
 #pragma unroll
     for (int x = 0; x < NX; ++x)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) g[x][r] = X[(off + x * sx + r * sr) * kPitch + lane];
+      for (int r = 0; r < NR; ++r) g[x][r] = X[(off + x * sx + r * sr) * P + lane];
   }
 }
 
@@ -1149,6 +1143,353 @@ hipError_t launch_mfma_shape(const FemArgs &a, bool ew, int grid, hipStream_t s)
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 matrix-core variant with (r, i) on the M side and the elements on N.
+// Stage 1 of a unit of 16 elements, T[(r, i), e] = sum_j S[r, i, j] u[e, j],
+// runs as v_mfma_f64_16x16x4f64 blocks (M = 16 (r, i) pairs, N = 16
+// elements, K = 4 values of j).  The rows are ordered so that the
+// accumulator layout hands every lane all NR values of T it needs: item v of
+// lane l holds row 4 v + l / 16 of each M block, so lane group q = l / 16
+// takes the i values [q IQ, (q + 1) IQ), IQ = ceil(NI / 4), and slot
+// s = 4 mb + v of the group holds (i = q IQ + s / NR, r = s % NR).  For P4
+// that is 105 useful rows of 112 (with i on the N side: 144 columns).  The j
+// axis is split the same way (lane group q' of the K side takes j in
+// [q' KQ, (q' + 1) KQ)), so one u value per lane and K block.  S is staged
+// once per block in LDS as A fragments.  Per unit a wave
+//   * stages the G row of its 16 elements (once per unit; the members share
+//     G) and forms G[x][r] of its lane's element in registers;
+//   * per member: u (and the second source of an element-wise u) arrive
+//     through coalesced 16-byte loads issued one work item ahead; the
+//     element-wise prologue runs on them, and LDS turns them into B
+//     fragments;
+//   * stage 2, out[e, x, i] = sum_r G[x][r] T[r, i], runs in registers; the
+//     unit's output block (contiguous: 16 x NX x NI values) goes through LDS
+//     to HBM as 16-byte streaming stores of whole lines.
+// ---------------------------------------------------------------------------
+template <int NI, int NJ, int NR, int NX>
+struct MfmaRI {
+  static constexpr int kU = 16;                             // elements per unit
+  static constexpr int kIQ = (NI + 3) / 4;                  // i values per lane group
+  static constexpr int kSlots = kIQ * NR;                   // (i, r) slots per lane group
+  static constexpr int kMB = (kSlots + 3) / 4;              // 16-row M blocks
+  static constexpr int kKQ = (NJ + 3) / 4;                  // K blocks
+  static constexpr int kFrags = kMB * kKQ;                  // A fragments of S
+  static constexpr int kOut = kU * NX * NI;                 // output values of a unit
+  static constexpr int kUVec = kU * NJ / 2;                 // 16-byte vectors of u per unit
+  static constexpr int kUT = (kUVec + kTile - 1) / kTile;   // u vectors per lane
+  static constexpr int kOVec = kOut / 2;
+  static constexpr int kOT = (kOVec + kTile - 1) / kTile;
+  static constexpr int kGP = kU + 1;                        // pitch of the staged G row
+  static constexpr int kGT = (kU * kMaxRow + kTile - 1) / kTile;
+  static constexpr int kStage0 = kOut > kU * NJ ? kOut : kU * NJ;
+  static constexpr int kStage1 = kStage0 > kMaxRow * kGP ? kStage0 : kMaxRow * kGP;
+  static constexpr int kStage = (kStage1 + 1) & ~1;         // 16-byte multiple
+};
+
+// UK: 0 plain u; 1 element-wise prologue on the groups that have one, one
+// source; 2 every group element-wise with two sources.
+template <int NI, int NJ, int NR, int NX, int UK>
+__global__ void __launch_bounds__(kTile * kMW) __attribute__((amdgpu_waves_per_eu(2)))
+    fem_mfma_ri_kernel(const FemArgs a) {
+  constexpr bool EW = UK > 0, TWO = UK == 2;
+  using M = MfmaRI<NI, NJ, NR, NX>;
+  using V2 = typename Vec16<double>::type;
+  __shared__ double Sf[M::kFrags * kTile];
+  __shared__ V2 Stage2[kMW * M::kStage / 2];
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kTile);
+  double *const X = (double *)Stage2 + wave * M::kStage;
+  V2 *const XV = Stage2 + wave * (M::kStage / 2);
+
+  // S as A fragments: fragment (mb, kb), lane l holds row m = 16 mb + l % 16
+  // (lane group q = m % 4, slot s = 4 mb + (l % 16) / 4) and j = (l / 16) KQ + kb.
+  {
+    const FemGroup &G0 = a.grp[0];
+    const double *__restrict__ S = (const double *)G0.S;
+    for (int f = threadIdx.x; f < M::kFrags * kTile; f += kTile * kMW) {
+      const int frag = f / kTile, l = f - frag * kTile;
+      const int mb = frag / M::kKQ, kb = frag - mb * M::kKQ;
+      const int ml = l % 16;
+      const int s = 4 * mb + ml / 4, q = ml % 4;
+      const int k = s / NR, r = s - k * NR;
+      const int i = q * M::kIQ + k, j = (l / 16) * M::kKQ + kb;
+      Sf[f] = (s < M::kSlots && i < NI && j < NJ)
+                  ? S[r * G0.ss[0] + i * G0.ss[1] + j * G0.ss[2]] : 0.0;
+    }
+    __syncthreads();
+  }
+
+  const int64_t u0 = a.tile0 * (kTile / M::kU), u1 = a.tile1 * (kTile / M::kU);
+  const int64_t nw = (int64_t)gridDim.x * kMW;
+  int64_t unit = u0 + (int64_t)blockIdx.x * kMW + wave;
+  if (unit >= u1) return;
+  const int ng = a.n_groups;
+  const FemSrc &gs = a.mem[0].g;
+  const int grow = a.grp[0].g_row;
+  const int gse = (int)gs.s0[0];
+
+  // Raw loads of one work item (unit, member group g): u, the second source
+  // of an element-wise u, and the unit's G row when g == 0.  Two sets
+  // alternate: the loads of item t + 2 are issued while item t computes.
+  struct Raw {
+    double u[2 * M::kUT];
+    double w[TWO ? 2 * M::kUT : 1];
+    double g[M::kGT];
+  };
+  auto load_item = [&](Raw &R, int64_t un, int g) {
+    const int lane = fresh_lane();
+    const FemGroup &G = a.grp[g];
+    const int64_t e0 = un * M::kU;
+    const V2 *__restrict__ pu = (const V2 *)((const double *)G.u.p0 + G.u.off0 + e0 * NJ);
+#pragma unroll
+    for (int t = 0; t < M::kUT; ++t) {
+      int qv = lane + kTile * t;
+      if ((t + 1) * kTile > M::kUVec) qv = qv < M::kUVec ? qv : M::kUVec - 1;
+      const V2 x = __builtin_nontemporal_load(&pu[qv]);
+      R.u[2 * t] = x[0];
+      R.u[2 * t + 1] = x[1];
+    }
+    if constexpr (TWO) {
+      const V2 *__restrict__ pw = (const V2 *)((const double *)G.u.p1 + G.u.off1 + e0 * NJ);
+#pragma unroll
+      for (int t = 0; t < M::kUT; ++t) {
+        int qv = lane + kTile * t;
+        if ((t + 1) * kTile > M::kUVec) qv = qv < M::kUVec ? qv : M::kUVec - 1;
+        const V2 x = __builtin_nontemporal_load(&pw[qv]);
+        R.w[2 * t] = x[0];
+        R.w[2 * t + 1] = x[1];
+      }
+    }
+    if (g == 0) {
+      const double *__restrict__ pg = (const double *)gs.p0 + a.grp[0].g_off + e0 * gse;
+      const int lim = (M::kU - 1) * gse + grow - 1;
+#pragma unroll
+      for (int t = 0; t < M::kGT; ++t) {
+        const int f = lane + kTile * t;
+        const int el = f / kMaxRow, c = f - el * kMaxRow;
+        const int pos = el * gse + c;
+        R.g[t] = pg[pos < lim ? pos : lim];
+      }
+    }
+  };
+
+  double gm[NX][NR];
+  // G[x][r] of this lane's element from the G row in R (first member of a unit).
+  auto stage_g = [&](const Raw &R) {
+    const int lane = fresh_lane();
+#pragma unroll
+    for (int t = 0; t < M::kGT; ++t) {
+      const int f = lane + kTile * t;
+      const int el = f / kMaxRow, c = f - el * kMaxRow;
+      if (f < M::kU * kMaxRow) X[c * M::kGP + el] = R.g[t];
+    }
+    wave_sync();
+    g_from_row<double, NX, NR, M::kGP>(X, gs, lane % 16, gm);
+    wave_sync();
+  };
+  // u values through LDS into B fragments: lane (n, q) takes u[n][q KQ + kb].
+  auto to_bf = [&](const double (&uv)[2 * M::kUT], double (&bf)[M::kKQ]) {
+    const int lane = fresh_lane();
+#pragma unroll
+    for (int t = 0; t < M::kUT; ++t) {
+      const int qv = lane + kTile * t;
+      if ((t + 1) * kTile <= M::kUVec || qv < M::kUVec) XV[qv] = V2{uv[2 * t], uv[2 * t + 1]};
+    }
+    wave_sync();
+    const int n = lane % 16, q = lane / 16;
+#pragma unroll
+    for (int kb = 0; kb < M::kKQ; ++kb) {
+      const int j = q * M::kKQ + kb;
+      bf[kb] = j < NJ ? X[n * NJ + j] : 0.0;
+    }
+    wave_sync();
+  };
+  auto mfma = [&](const double (&bf)[M::kKQ], d4v (&acc)[M::kMB]) {
+    const int lane = fresh_lane();
+#pragma unroll
+    for (int mb = 0; mb < M::kMB; ++mb) acc[mb] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < M::kKQ; ++kb)
+#pragma unroll
+      for (int mb = 0; mb < M::kMB; ++mb)
+        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Sf[(mb * M::kKQ + kb) * kTile + lane],
+                                                       bf[kb], acc[mb], 0, 0, 0);
+  };
+  // Stage 1 of the current item on the matrix cores; meanwhile the next
+  // item's u values (uv, from R) get their element-wise prologue on the
+  // vector ALUs: the two share one basic block so the scheduler interleaves
+  // them.
+  auto mfma_and_prologue = [&](const double (&bf)[M::kKQ], d4v (&acc)[M::kMB], bool next,
+                               const Raw &R, int gn, double (&uv)[2 * M::kUT]) {
+#pragma unroll
+    for (int k = 0; k < 2 * M::kUT; ++k) uv[k] = R.u[k];
+    if (!next) {
+      mfma(bf, acc);
+      return;
+    }
+    if constexpr (EW) {
+      const FemSrc &u = a.grp[gn].u;
+      if (u.kind == FEM_SRC_ELEMENTWISE) {
+        const double alpha = u.alpha, beta = u.beta;
+        const int op = u.op;
+        bool small = true;
+#pragma unroll
+        for (int k = 0; k < 2 * M::kUT; ++k) small = small && fabs(uv[k]) < 0x1p20;
+        const bool trig = op == BES_OP_SIN || op == BES_OP_COS;
+        if (trig && __builtin_amdgcn_ballot_w64(!small) == 0) {
+          // sin / cos: the short reduction (every value of the wave below 2^20)
+          const int shift = op == BES_OP_COS ? 1 : 0;
+          mfma(bf, acc);
+#pragma unroll
+          for (int k = 0; k < 2 * M::kUT; ++k)
+            uv[k] = alpha * sincos_small(uv[k], shift) + beta + (TWO ? R.w[k] : 0.0);
+          // issue order: each matrix instruction followed by a run of the
+          // prologue's vector instructions, which execute in its shadow
+#pragma unroll
+          for (int k = 0; k < M::kFrags; ++k) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);   // VALU
+          }
+        } else {
+          mfma(bf, acc);
+#pragma unroll
+          for (int k = 0; k < 2 * M::kUT; ++k)
+            uv[k] = alpha * apply_op<double>(op, uv[k]) + beta + (TWO ? R.w[k] : 0.0);
+        }
+        return;
+      }
+    }
+    mfma(bf, acc);
+  };
+  // Stage 2 of item (un, g) in the accumulator layout; the unit's output
+  // block goes through LDS to HBM.
+  auto stage2 = [&](const d4v (&acc)[M::kMB], int64_t un, int g) {
+    const int lane = fresh_lane();
+    const int n = lane % 16, q = lane / 16;
+#pragma unroll
+    for (int k = 0; k < M::kIQ; ++k) {
+      const int i = q * M::kIQ + k;
+#pragma unroll
+      for (int x = 0; x < NX; ++x) {
+        double o = 0.0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const int s = k * NR + r;
+          o = fma(gm[x][r], acc[s / 4][s % 4], o);
+        }
+        if (i < NI) X[n * (NX * NI) + x * NI + i] = o;
+      }
+    }
+    wave_sync();
+    V2 *__restrict__ ov = (V2 *)((double *)a.mem[a.grp[g].m0].out + un * M::kU * (NX * NI));
+#pragma unroll
+    for (int t = 0; t < M::kOT; ++t) {
+      const int qv = lane + kTile * t;
+      if ((t + 1) * kTile <= M::kOVec || qv < M::kOVec) {
+        const V2 vv = XV[qv];
+        __builtin_nontemporal_store(vv, &ov[qv]);
+      }
+    }
+    wave_sync();
+  };
+  // One item k: its G row (first member of a unit) from Rk, the loads of
+  // item k + 2 into Rk, stage 1 of k with the prologue of k + 1 (raw in Rn),
+  // the B fragments of k + 1, stage 2 of k.
+  double bf[M::kKQ];
+  auto step = [&](Raw &Rk, const Raw &Rn, int64_t uk, int gk, bool v1, int g1, bool v2,
+                  int64_t u2, int g2) {
+    if (gk == 0) stage_g(Rk);
+    if (v2) load_item(Rk, u2, g2);
+    d4v acc[M::kMB];
+    double uv[2 * M::kUT];
+    mfma_and_prologue(bf, acc, v1, Rn, g1, uv);
+    if (v1) to_bf(uv, bf);
+    stage2(acc, uk, gk);
+  };
+
+  // items in order: (unit, 0..ng-1), then the wave's next unit
+  auto advance = [&](int64_t &un, int &g) {
+    if (++g == ng) {
+      g = 0;
+      un += nw;
+    }
+  };
+  Raw A, B;
+  int64_t ua = unit, ub = unit, uc;
+  int ga = 0, gb = 0, gc;
+  advance(ub, gb);
+  load_item(A, ua, ga);
+  if (ub < u1) load_item(B, ub, gb);
+  {
+    // the first item's prologue and B fragments, not overlapped
+    d4v acc[M::kMB];
+    double uv[2 * M::kUT];
+    (void)acc;
+#pragma unroll
+    for (int k = 0; k < 2 * M::kUT; ++k) uv[k] = A.u[k];
+    if constexpr (EW) {
+      const FemSrc &u = a.grp[ga].u;
+      if (u.kind == FEM_SRC_ELEMENTWISE) {
+#pragma unroll
+        for (int k = 0; k < 2 * M::kUT; ++k)
+          uv[k] = u.alpha * apply_op<double>(u.op, uv[k]) + u.beta + (TWO ? A.w[k] : 0.0);
+      }
+    }
+    to_bf(uv, bf);
+  }
+  while (true) {
+    // A: item a (G row pending), B: item b = a + 1; item c = b + 1 into A
+    uc = ub;
+    gc = gb;
+    advance(uc, gc);
+    step(A, B, ua, ga, ub < u1, gb, uc < u1, uc, gc);
+    if (ub >= u1) break;
+    ua = uc;
+    ga = gc;
+    // B: item b (G row pending), A: item a = b + 1; the item after into B
+    uc = ua;
+    gc = ga;
+    advance(uc, gc);
+    step(B, A, ub, gb, ua < u1, ga, uc < u1, uc, gc);
+    if (ua >= u1) break;
+    ub = uc;
+    gb = gc;
+  }
+}
+
+// Source kind of the groups' u for fem_mfma_ri_kernel (its UK), or -1 when
+// the groups mix one- and two-source element-wise operands.
+int ri_u_kind(const FemArgs &a) {
+  bool any_ew = false, any_two = false, all_two = true;
+  for (int g = 0; g < a.n_groups; ++g) {
+    const FemSrc &u = a.grp[g].u;
+    const bool ew = u.kind == FEM_SRC_ELEMENTWISE;
+    any_ew |= ew;
+    any_two |= ew && u.p1 != nullptr;
+    all_two &= ew && u.p1 != nullptr;
+  }
+  if (!any_ew) return 0;
+  if (all_two) return 2;
+  return any_two ? -1 : 1;
+}
+
+template <int NI, int NJ, int NR, int NX>
+hipError_t launch_mfma_ri_shape(const FemArgs &a, int uk, int grid, hipStream_t s) {
+  if constexpr (mfma_shape(NI, NJ, NR)) {
+    const dim3 block(kTile * kMW);
+    if (uk == 2)
+      hipLaunchKernelGGL((fem_mfma_ri_kernel<NI, NJ, NR, NX, 2>), dim3(grid), block, 0, s, a);
+    else if (uk == 1)
+      hipLaunchKernelGGL((fem_mfma_ri_kernel<NI, NJ, NR, NX, 1>), dim3(grid), block, 0, s, a);
+    else if (uk == 0)
+      hipLaunchKernelGGL((fem_mfma_ri_kernel<NI, NJ, NR, NX, 0>), dim3(grid), block, 0, s, a);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 // Split groups with more than `mpg` members into several groups that share
 // S and U (T is then recomputed per chunk).
 FemArgs chunk_groups(const FemArgs &in, int mpg, int *group_of_chunk) {
@@ -1371,8 +1712,14 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
     d.tile1 = full_tiles;
     const int64_t blocks = std::min<int64_t>((full_tiles + kMW - 1) / kMW,
                                              (int64_t)device_cu_count() * std::max(1, blocks_per_cu / kMW));
-#define BES_FEM_MFMA_DISPATCH(ni, nj, nr, nx)                                                   \
-    if (NI == ni && NJ == nj && NR == nr && NX == nx) e = launch_mfma_shape<ni, nj, nr, nx>(d, ew, (int)blocks, stream);
+    // variant 1, or groups that mix one- and two-source element-wise u: i
+    // on the N side; otherwise (r, i) on the M side
+    const int uk = ri_u_kind(d);
+    const bool ri = variant != 1 && uk >= 0;
+#define BES_FEM_MFMA_DISPATCH(ni, nj, nr, nx)                                              \
+    if (NI == ni && NJ == nj && NR == nr && NX == nx)                                      \
+      e = ri ? launch_mfma_ri_shape<ni, nj, nr, nx>(d, uk, (int)blocks, stream)            \
+             : launch_mfma_shape<ni, nj, nr, nx>(d, ew, (int)blocks, stream);
     e = hipErrorInvalidValue;
     BES_FEM_SHAPES(BES_FEM_MFMA_DISPATCH)
 #undef BES_FEM_MFMA_DISPATCH

@@ -85,6 +85,29 @@ def test_config2_full_size(ctx, dtype):
     _check_sampled(p, w)
 
 
+def test_config2_full_size_whole_output_every_candidate(ctx):
+    """The P3 gradient batch at full size (e = 2^20, FP64), every output
+    element against the oracle, in every FEM-stream configuration the tuner
+    may record for it (the launch the benchmark times is one of them)."""
+    from paper_2601_12220_amd import tune
+    w = workloads.config2(dtype="float64")
+    p = ctx.register(w.notation, w.table, w.operands)
+    assert p.template == "fem_stream"
+    bufs = device_buffers(w)
+    ref = oracle_full(w)
+    outs = [torch.empty(w.out_shape(), dtype=torch.float64, device="cuda") for _ in range(w.b)]
+    for cand in tune.candidates(capi.BES_T_FEM_STREAM):
+        _say(f"[parity-full] {w.name} config={cand}")
+        for o in outs:
+            o.fill_(float("nan"))
+        p.set_config(*cand)
+        p.launch(bufs, outs)
+        torch.cuda.synchronize()
+        for m in range(w.b):
+            err = rel_fro(outs[m].cpu().numpy(), ref[m])
+            assert err <= TOL["float64"], (cand, m, err)
+
+
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 @pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("bpc", [1, 64])
@@ -146,6 +169,70 @@ def test_functional_trig_ranges(ctx, op):
     w2 = workloads.Workload(w.name + "_" + op, w.notation, w.table, ops, bufs, w.dtype, w.info)
     p = ctx.register(w2.notation, w2.table, w2.operands)
     assert p.template == "fem_stream"
+    _check_full(p, w2)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("bpc", [8, 64])
+def test_config3_matrix_core_mappings(ctx, variant, bpc):
+    """The functional P4 batch on both matrix-core mappings ((r, i) on the M
+    side: variant 0; i on the N side: variant 1) with a ragged tail, each
+    wave walking several 16-element units and all four members."""
+    w = workloads.config3(e=64 * 1093 + 29)
+    p = ctx.register(w.notation, w.table, w.operands)
+    assert p.template == "fem_stream"
+    p.set_config(capi.BES_T_FEM_STREAM, 64, bpc, variant)
+    _check_full(p, w)
+
+
+@pytest.mark.parametrize("nx", [3, 1])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_p4_matrix_core_plain_operands(ctx, nx, variant):
+    """P4 gradient batches whose operands are plain arrays (no element-wise
+    prologue), with G[e, x, r] and with G[e, r] (x absent), on both
+    matrix-core mappings, ragged tail."""
+    e = 64 * 301 + 17
+    dt = "float64"
+    gshape = (e, 3, 3) if nx == 3 else (e, 3)
+    bufs = {"D": workloads._uniform(11, 0, (3, 35, 35), -1.0, 1.0, dt),
+            "G": workloads._normal(11, 1, gshape, dt)}
+    ops = {k: workloads._dense(k, v, dt) for k, v in bufs.items()}
+    table = []
+    for k in range(3):
+        bufs[f"u{k}"] = workloads._normal(11, 2 + k, (e, 35), dt)
+        ops[f"u{k}"] = workloads._dense(f"u{k}", bufs[f"u{k}"], dt)
+        table.append(["D", "G", f"u{k}"])
+    nota = "rij,exr,ej->exi" if nx == 3 else "rij,er,ej->ei"
+    w = workloads.Workload(f"p4_plain_x{nx}", nota, table, ops, bufs, dt, {"e": e})
+    p = ctx.register(w.notation, w.table, w.operands)
+    assert p.template == "fem_stream"
+    p.set_config(capi.BES_T_FEM_STREAM, 64, 16, variant)
+    _check_full(p, w)
+
+
+@pytest.mark.parametrize("mix", ["one_source", "one_and_two", "plain_and_two", "plain_and_one"])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_p4_matrix_core_operand_mixes(ctx, mix, variant):
+    """The P4 batch with its members' u in different forms: element-wise
+    with one source (alpha*sin(a)+beta), mixed with two-source ones, and
+    mixed with plain arrays -- the kernel's per-group prologue and the
+    launcher's choice between the matrix-core mappings -- ragged tail."""
+    import dataclasses
+    w = workloads.config3(e=64 * 301 + 17)
+    ops = dict(w.operands)
+    for k in range(4):
+        u = ops[f"u{k}"]
+        one = dataclasses.replace(u, sources=(f"a{k}",), alpha=0.75, beta=-0.25)
+        plain = workloads._dense(f"a{k}", w.buffers[f"a{k}"], w.dtype)
+        if mix == "one_source" or (mix in ("one_and_two", "plain_and_one") and k >= 2):
+            ops[f"u{k}"] = one
+        if mix.startswith("plain") and k == 0:
+            ops[f"u{k}"] = dataclasses.replace(plain, name="u0")
+    w2 = workloads.Workload(w.name + "_" + mix, w.notation, w.table, ops, w.buffers, w.dtype,
+                            w.info)
+    p = ctx.register(w2.notation, w2.table, w2.operands)
+    assert p.template == "fem_stream"
+    p.set_config(capi.BES_T_FEM_STREAM, 64, 16, variant)
     _check_full(p, w2)
 
 
