@@ -63,8 +63,9 @@ def torch_dtype(name):
     return {"float32": torch.float32, "float64": torch.float64}[name]
 
 
-def algorithmic_bytes(w):
-    """Each distinct source buffer read once plus each output written once."""
+def algorithmic_split(w):
+    """(bytes read, bytes written): each distinct source buffer read once,
+    each output written once."""
     item = 8 if w.dtype == "float64" else 4
     used = set()
     for row in w.table:
@@ -74,7 +75,11 @@ def algorithmic_bytes(w):
     out = 1
     for s in w.out_shape():
         out *= s
-    return src + w.b * out * item
+    return src, w.b * out * item
+
+
+def algorithmic_bytes(w):
+    return sum(algorithmic_split(w))
 
 
 def fem_flops(w):
@@ -258,8 +263,10 @@ def run_fem(w, min_s, tune_first=True):
     ms, med, n = graph_time(lambda k, h: plan.launch_ptrs(ptrs[k][0], ptrs[k][1], h), n_sets,
                             min_s)
     cfg = plan.config
+    rd, wr = algorithmic_split(w)
     res = {"ms": ms, "ms_median": med, "steps_timed": n, "buffer_sets": n_sets,
-           "gbs": nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes,
+           "gbs": nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes, "bytes_read": rd,
+           "bytes_written": wr,
            "template": plan.template, "register_us": reg, "key": plan.key,
            "config": [cfg.template_id] + [int(cfg.p[k]) for k in range(4)], "tuned": tuned}
     fl = fem_flops(w)
@@ -270,10 +277,23 @@ def run_fem(w, min_s, tune_first=True):
     return res
 
 
-def fem_line(r, copy_gbs, peak_tflops):
+def attainable_frac(r, bws):
+    """Time the step's bytes take at the measured stream rates (reads at the
+    read rate, writes at the write rate, one after the other) over the
+    measured step time."""
+    if not bws or not bws.get("read") or not bws.get("write"):
+        return None
+    t = r["bytes_read"] / (bws["read"] * 1e9) + r["bytes_written"] / (bws["write"] * 1e9)
+    return round(t / (r["ms"] * 1e-3), 4)
+
+
+def fem_line(r, bws, peak_tflops):
+    copy_gbs = bws.get("copy") if bws else None
     line = {"GB/s": round(r["gbs"], 1), "ms": round(r["ms"], 5),
             "frac_hbm": round(r["gbs"] / HBM_PEAK_GBS, 4),
             "frac_copy": round(r["gbs"] / copy_gbs, 4) if copy_gbs else None,
+            "frac_attainable": attainable_frac(r, bws),
+            "write_share": round(r["bytes_written"] / r["bytes"], 3),
             "buffer_sets": r["buffer_sets"], "steps_timed": r["steps_timed"],
             "template": r["template"], "tuned_config": r["config"],
             "register_us": round(r["register_us"], 1)}
@@ -283,7 +303,7 @@ def fem_line(r, copy_gbs, peak_tflops):
     return line
 
 
-def run_apply_sweep(min_s, copy_gbs):
+def run_apply_sweep(min_s, bws):
     """Face mass and local divergence at the paper's shapes: P1..P4,
     e = 10^5, b in {1, 4, 8}, FP64, each point tuned first (records keyed by
     its canonical form), as the paper tunes every einsum."""
@@ -298,7 +318,7 @@ def run_apply_sweep(min_s, copy_gbs):
                 w = fn(p=p, e=100_000, b=b)
                 log(f"[bench] {w.name} b={b} e=1e5 FP64")
                 r = run_fem(w, min_s, tune_first=True)
-                rows[f"p{p}_b{b}"] = fem_line(r, copy_gbs, FP64_PEAK_TFLOPS)
+                rows[f"p{p}_b{b}"] = fem_line(r, bws, FP64_PEAK_TFLOPS)
         out[cls] = {"workload": f"{cls}: e=10^5, P1..P4, FP64, b members sharing the "
                                 "reference matrix and the geometry terms",
                     "key_p3_b4": ctx.register(*_nt(fn(p=3, e=100_000, b=4))).key,
@@ -310,7 +330,7 @@ def _nt(w):
     return w.notation, w.table, w.operands
 
 
-def run_tccg(min_s, copy_gbs, cases=24):
+def run_tccg(min_s, cases=24):
     """Binary contractions with affine operands (alpha_1 A + beta_1)(alpha_2 B +
     beta_2) in FP64, the TCCG extension of the paper, on the seeded stand-in
     generator (the suite itself is not available), each case tuned first.
@@ -498,13 +518,22 @@ def run_dense(min_s):
     return res
 
 
-def copy_bandwidth(min_s=1.0):
-    """Device-to-device copy of 1 GiB (read 1 GiB + write 1 GiB), GB/s."""
+def stream_bandwidths(min_s=1.0):
+    """Rates of plain device kernels on 1 GiB FP64 buffers, GB/s: copy (read
+    1 GiB + write 1 GiB), fill (write only) and sum (read only).  On this
+    memory system writes stream markedly slower than reads, so a step's
+    attainable time is its read bytes at the read rate plus its write bytes
+    at the write rate."""
     import torch
     a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    ms, n = time_eager(lambda: b.copy_(a), 10, 3, min_s)
-    return 2 * a.numel() * 8 / (ms * 1e-3) / 1e9
+    nbytes = a.numel() * 8
+    ms_copy, _ = time_eager(lambda: b.copy_(a), 10, 3, min_s)
+    ms_fill, _ = time_eager(lambda: b.fill_(1.0), 10, 3, min_s)
+    ms_sum, _ = time_eager(lambda: a.sum(), 10, 3, min_s)
+    return {"copy": 2 * nbytes / (ms_copy * 1e-3) / 1e9,
+            "write": nbytes / (ms_fill * 1e-3) / 1e9,
+            "read": nbytes / (ms_sum * 1e-3) / 1e9}
 
 
 def cpu_model():
@@ -603,23 +632,25 @@ def main():
             else {"f32", "p4", "apply", "tccg", "canon", "tiny", "batch", "dense"})
     min_s = args.min_time
 
-    log("[bench] copy bandwidth (1 GiB device-to-device)")
-    copy_gbs = copy_bandwidth()
-    extra = {"copy_GB/s": round(copy_gbs, 1)}
+    log("[bench] stream rates (1 GiB copy, fill, sum)")
+    bws = stream_bandwidths()
+    copy_gbs = bws["copy"]
+    extra = {"copy_GB/s": round(copy_gbs, 1), "fill_write_GB/s": round(bws["write"], 1),
+             "sum_read_GB/s": round(bws["read"], 1)}
     log("[bench] fem_grad_p3 FP64 e=2^20")
     head = run_fem(workloads.config2(dtype="float64"), min_s)
     if "f32" in only:
         log("[bench] fem_grad_p3 FP32 e=2^20")
         r = run_fem(workloads.config2(dtype="float32"), min_s)
-        extra["fem_grad_p3_f32"] = fem_line(r, copy_gbs, FP32_PEAK_TFLOPS)
+        extra["fem_grad_p3_f32"] = fem_line(r, bws, FP32_PEAK_TFLOPS)
     if "p4" in only:
         log("[bench] fem_grad_functional_p4 FP64 e=2^19")
         r = run_fem(workloads.config3(), min_s)
-        extra["fem_grad_functional_p4_f64"] = fem_line(r, copy_gbs, FP64_PEAK_TFLOPS)
+        extra["fem_grad_functional_p4_f64"] = fem_line(r, bws, FP64_PEAK_TFLOPS)
     if "apply" in only:
-        extra.update(run_apply_sweep(args.sweep_min_time, copy_gbs))
+        extra.update(run_apply_sweep(args.sweep_min_time, bws))
     if "tccg" in only:
-        extra["tccg_affine_f64"] = run_tccg(args.sweep_min_time, copy_gbs, args.tccg_cases)
+        extra["tccg_affine_f64"] = run_tccg(args.sweep_min_time, args.tccg_cases)
     if "canon" in only:
         log("[bench] canonicalization time per batched einsum (host)")
         extra["canonicalization_us"] = run_canonicalization()
@@ -664,6 +695,7 @@ def main():
                      "kernel": "fem_lean_kernel (FP64, i=j=20, r=3, 3 members); the step's "
                                "9.6 KB re-layout of D is charged to it",
                      "frac_copy": round(head["gbs"] / copy_gbs, 4),
+                     "frac_attainable": attainable_frac(head, bws),
                      "step_us": round(head["ms"] * 1e3, 2)},
         "cpu_baseline": cpu,
         "extra": dict(extra, fem_grad_p3_f64_tflops=round(head.get("tflops", 0.0), 2)),
