@@ -116,7 +116,7 @@ def definitional_flops(w):
 def kernel_source_digest():
     h = hashlib.sha256()
     for rel in ("paper_2601_12220_amd/csrc/kernels/fem_stream.hip",
-                "paper_2601_12220_amd/csrc/fem_shapes.h", "paper_2601_12220_amd/csrc/desc.h"):
+                "paper_2601_12220_amd/csrc/fem_shapes.h"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
