@@ -116,7 +116,10 @@ enum bes_template {
                             variant: 0 the lean kernel with two waves per
                             64-element tile where the batch allows it, 2 the
                             lean kernel with one wave per tile, 1 always the
-                            descriptor-driven kernel; for the face-mass /
+                            descriptor-driven kernel, 3 for FP32 batches of
+                            one stage-1 group (at most three members, plain
+                            u, G views of one row) stage 1 on the matrix
+                            cores (other batches as 0); for the face-mass /
                             divergence class p[1] = blocks of four waves
                             per compute unit, p[2] = 0 or 1 the shared
                             matrix in LDS, 2 as scalar operands */

@@ -367,7 +367,7 @@ int bes_plan_set_config(bes_plan *plan, const bes_config *cfg) {
   }
   if (c.template_id == BES_T_FEM_STREAM) {
     if (c.p[1] < 0 || c.p[1] > 64) return fail(BES_E_INVALID, "blocks per CU must be 0..64");
-    if (c.p[2] < 0 || c.p[2] > 2) return fail(BES_E_INVALID, "FEM kernel variant must be 0, 1 or 2");
+    if (c.p[2] < 0 || c.p[2] > 3) return fail(BES_E_INVALID, "FEM kernel variant must be 0, 1, 2 or 3");
   }
   plan->p.cfg = c;
   return BES_OK;

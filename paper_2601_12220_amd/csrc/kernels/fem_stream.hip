@@ -1490,6 +1490,190 @@ hipError_t launch_mfma_ri_shape(const FemArgs &a, int uk, int grid, hipStream_t 
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 matrix-core variant of the gradient class for one stage-1 group (its
+// members share S and u; each has its own G view and output).  Stage 1 of 16
+// elements runs on v_mfma_f32_16x16x4f32 with (r, i) on the M side, laid out
+// so that each lane ends with all NR values of T for its i values: the FP32
+// accumulator holds row 4 (lane / 16) + v of each block in item v, so lane
+// group q takes slots s = 4 mb + v with i = q IQ + s / NR, r = s % NR (for
+// P3: 60 useful rows of 64, K = 20 exactly).  Stage 2 runs per member in
+// registers.  u comes in and each member's output block goes out through a
+// small per-wave LDS area with 16-byte accesses; units of 16 elements are
+// dealt to the grid's waves in turn, the next unit's loads in flight while
+// the current one computes.
+// ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <int NI, int NJ, int NR, int NX>
+struct Mfma32 {
+  static constexpr int kU = 16;                             // elements per unit
+  static constexpr int kIQ = (NI + 3) / 4;                  // i values per lane group
+  static constexpr int kSlots = kIQ * NR;                   // (i, r) slots per lane group
+  static constexpr int kMB = (kSlots + 3) / 4;              // 16-row M blocks
+  static constexpr int kKQ = (NJ + 3) / 4;                  // K blocks
+  static constexpr int kFrags = kMB * kKQ;                  // A fragments of S
+  static constexpr int kOut = kU * NX * NI;                 // output values of a member
+  static constexpr int kUVec = kU * NJ / 4;                 // 16-byte vectors of u
+  static constexpr int kUT = (kUVec + kTile - 1) / kTile;
+  static constexpr int kOVec = kOut / 4;
+  static constexpr int kOT = (kOVec + kTile - 1) / kTile;
+  static constexpr int kGP = kU + 1;                        // pitch of the staged G row
+  static constexpr int kGT = (kU * kMaxRow + kTile - 1) / kTile;
+  static constexpr int kStage0 = kOut > kU * NJ ? kOut : kU * NJ;
+  static constexpr int kStage1 = kStage0 > kMaxRow * kGP ? kStage0 : kMaxRow * kGP;
+  static constexpr int kStage = (kStage1 + 3) & ~3;         // 16-byte multiple
+};
+constexpr int kMW32 = 4;        // waves per block
+constexpr int kMaxMem32 = 3;    // members of the group
+
+template <int NI, int NJ, int NR, int NX>
+__global__ void __launch_bounds__(kTile * kMW32) fem_mfma32_kernel(const FemArgs a) {
+  using M = Mfma32<NI, NJ, NR, NX>;
+  using V4 = typename Vec16<float>::type;
+  __shared__ float Sf[M::kFrags * kTile];
+  __shared__ V4 Stage4[kMW32 * M::kStage / 4];
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kTile);
+  float *const X = (float *)Stage4 + wave * M::kStage;
+  V4 *const XV = Stage4 + wave * (M::kStage / 4);
+  const FemGroup &G = a.grp[0];
+
+  // S as A fragments: fragment (mb, kb), lane l holds row m = 16 mb + l % 16
+  // (lane group q = (l % 16) / 4, slot s = 4 mb + l % 4) and j = (l / 16) KQ + kb.
+  {
+    const float *__restrict__ S = (const float *)G.S;
+    for (int f = threadIdx.x; f < M::kFrags * kTile; f += kTile * kMW32) {
+      const int frag = f / kTile, l = f - frag * kTile;
+      const int mb = frag / M::kKQ, kb = frag - mb * M::kKQ;
+      const int ml = l % 16;
+      const int s = 4 * mb + ml % 4, q = ml / 4;
+      const int k = s / NR, r = s - k * NR;
+      const int i = q * M::kIQ + k, j = (l / 16) * M::kKQ + kb;
+      Sf[f] = (s < M::kSlots && i < NI && j < NJ)
+                  ? S[r * G.ss[0] + i * G.ss[1] + j * G.ss[2]] : 0.0f;
+    }
+    __syncthreads();
+  }
+
+  const int64_t u0 = a.tile0 * (kTile / M::kU), u1 = a.tile1 * (kTile / M::kU);
+  const int64_t nw = (int64_t)gridDim.x * kMW32;
+  int64_t unit = u0 + (int64_t)blockIdx.x * kMW32 + wave;
+  if (unit >= u1) return;
+  const int nm = a.n_members;
+  const FemSrc &gs = a.mem[0].g;
+  const int grow = G.g_row;
+  const int gse = (int)gs.s0[0];
+
+  V4 ru[M::kUT];
+  float rg[M::kGT];
+  auto load = [&](int64_t un) {
+    const int lane = fresh_lane();
+    const int64_t e0 = un * M::kU;
+    const V4 *__restrict__ pu = (const V4 *)((const float *)G.u.p0 + G.u.off0 + e0 * NJ);
+#pragma unroll
+    for (int t = 0; t < M::kUT; ++t) {
+      int qv = lane + kTile * t;
+      if ((t + 1) * kTile > M::kUVec) qv = qv < M::kUVec ? qv : M::kUVec - 1;
+      ru[t] = __builtin_nontemporal_load(&pu[qv]);
+    }
+    const float *__restrict__ pg = (const float *)gs.p0 + G.g_off + e0 * gse;
+    const int lim = (M::kU - 1) * gse + grow - 1;
+#pragma unroll
+    for (int t = 0; t < M::kGT; ++t) {
+      const int f = lane + kTile * t;
+      const int el = f / kMaxRow, c = f - el * kMaxRow;
+      const int pos = el * gse + c;
+      rg[t] = pg[pos < lim ? pos : lim];
+    }
+  };
+  load(unit);
+  while (true) {
+    const int lane = fresh_lane();
+    const int n = lane % 16, q = lane / 16;
+    const int64_t e0 = unit * M::kU;
+    // ---- G of this lane's element for every member, from the staged row --
+#pragma unroll
+    for (int t = 0; t < M::kGT; ++t) {
+      const int f = lane + kTile * t;
+      const int el = f / kMaxRow, c = f - el * kMaxRow;
+      if (f < M::kU * kMaxRow) X[c * M::kGP + el] = rg[t];
+    }
+    wave_sync();
+    float gm[kMaxMem32][NX][NR];
+#pragma unroll
+    for (int m = 0; m < kMaxMem32; ++m)
+      if (m < nm) g_from_row<float, NX, NR, M::kGP>(X, a.mem[m].g, n, gm[m]);
+    wave_sync();
+    // ---- u through LDS into B fragments -----------------------------------
+#pragma unroll
+    for (int t = 0; t < M::kUT; ++t) {
+      const int qv = lane + kTile * t;
+      if ((t + 1) * kTile <= M::kUVec || qv < M::kUVec) XV[qv] = ru[t];
+    }
+    wave_sync();
+    float bf[M::kKQ];
+#pragma unroll
+    for (int kb = 0; kb < M::kKQ; ++kb) {
+      const int j = q * M::kKQ + kb;
+      bf[kb] = j < NJ ? X[n * NJ + j] : 0.0f;
+    }
+    wave_sync();
+    // ---- the next unit's loads, in flight during this one -----------------
+    const int64_t next = unit + nw;
+    const bool more = next < u1;
+    if (more) load(next);
+    // ---- stage 1 on the matrix cores -------------------------------------
+    f4v acc[M::kMB];
+#pragma unroll
+    for (int mb = 0; mb < M::kMB; ++mb) acc[mb] = f4v{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < M::kKQ; ++kb)
+#pragma unroll
+      for (int mb = 0; mb < M::kMB; ++mb)
+        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Sf[(mb * M::kKQ + kb) * kTile + lane],
+                                                       bf[kb], acc[mb], 0, 0, 0);
+    // ---- stage 2 per member, output block through LDS ---------------------
+#pragma unroll
+    for (int m = 0; m < kMaxMem32; ++m) {
+      if (m >= nm) break;
+#pragma unroll
+      for (int k = 0; k < M::kIQ; ++k) {
+        const int i = q * M::kIQ + k;
+#pragma unroll
+        for (int x = 0; x < NX; ++x) {
+          float o = 0.0f;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const int s = k * NR + r;
+            o = fmaf(gm[m][x][r], acc[s / 4][s % 4], o);
+          }
+          if (i < NI) X[n * (NX * NI) + x * NI + i] = o;
+        }
+      }
+      wave_sync();
+      V4 *__restrict__ ov = (V4 *)((float *)a.mem[m].out + e0 * (NX * NI));
+#pragma unroll
+      for (int t = 0; t < M::kOT; ++t) {
+        const int qv = lane + kTile * t;
+        if ((t + 1) * kTile <= M::kOVec || qv < M::kOVec) {
+          const V4 vv = XV[qv];
+          __builtin_nontemporal_store(vv, &ov[qv]);
+        }
+      }
+      wave_sync();
+    }
+    if (!more) break;
+    unit = next;
+  }
+}
+
+template <int NI, int NJ, int NR, int NX>
+hipError_t launch_mfma32_shape(const FemArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((fem_mfma32_kernel<NI, NJ, NR, NX>), dim3(grid), dim3(kTile * kMW32), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
 // Split groups with more than `mpg` members into several groups that share
 // S and U (T is then recomputed per chunk).
 FemArgs chunk_groups(const FemArgs &in, int mpg, int *group_of_chunk) {
@@ -1573,40 +1757,6 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
     FemMember &M = c.mem[m];
     M.o_dense = (M.oe == (int64_t)NX * NI && (NX == 1 || M.ox == NI) && M.oi == 1) ? 1 : 0;
   }
-  // S is read in place when it is dense [r][i][j]; other layouts are packed
-  // into that layout first (one small kernel, only when needed).
-  PackArgs pk;
-  pk.n_groups = c.n_groups;
-  pk.NR = NR;
-  pk.NI = NI;
-  pk.NJ = NJ;
-  bool need_pack = false;
-  pk.transposed = chunks_of(f64, NI, NR) == 1 ? 1 : 0;
-  for (int k = 0; k < c.n_groups; ++k) {
-    FemGroup &G = c.grp[k];
-    const bool dense = !pk.transposed && G.ss[2] == 1 && (NI == 1 || G.ss[1] == NJ) &&
-                       (NR == 1 || G.ss[0] == (int64_t)NI * NJ);
-    G.s_dense = dense ? 1 : 0;
-    pk.S[k] = dense ? nullptr : G.S;
-    pk.sr[k] = G.ss[0];
-    pk.si[k] = G.ss[1];
-    pk.sj[k] = G.ss[2];
-    need_pack |= !dense;
-  }
-  hipError_t e = hipSuccess;
-  if (need_pack) {
-    const int pack_total = NR * NI * NJ * c.n_groups;
-    dim3 pgrid((pack_total + 255) / 256);
-    if (f64)
-      hipLaunchKernelGGL(pack_s_kernel<double>, pgrid, dim3(256), 0, stream, pk,
-                         (double *)workspace);
-    else
-      hipLaunchKernelGGL(pack_s_kernel<float>, pgrid, dim3(256), 0, stream, pk,
-                         (float *)workspace);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (blocks_per_cu < 1) blocks_per_cu = 1;
   // Full dense tiles go to the straight-line FAST instantiation; the last
   // partial tile and any other layout to the general one.
   bool fast_ok = true;
@@ -1630,6 +1780,63 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
   for (int m = 0; m < c.n_members && fast_ok; ++m) fast_ok = al16(c.mem[m].out, 0, esz);
   const int64_t tiles = (a.E + kTile - 1) / kTile;
   const int64_t full_tiles = fast_ok ? a.E / kTile : 0;
+  // FP32 matrix-core variant (p[2] = 3): one stage-1 group of at most three
+  // members, plain u, every member's G a view of one staged row (or the
+  // tetrahedron rows), full dense tiles.  It reads S in place.
+  bool use_mfma32 = variant == 3 && !f64 && fast_ok && full_tiles > 0 && !ew &&
+                    c.n_groups == 1 && c.grp[0].m0 == 0 && c.grp[0].m1 == c.n_members &&
+                    c.n_members >= 1 && c.n_members <= kMaxMem32 && c.grp[0].g_row > 0 &&
+                    c.grp[0].g_row <= kMaxRow && c.mem[0].g.s0[0] > 0 &&
+                    c.mem[0].g.s0[0] <= INT32_MAX;
+  for (int m = 0; m < c.n_members && use_mfma32; ++m) {
+    const FemSrc &g = c.mem[m].g;
+    if (g.kind == FEM_SRC_TET) {
+      use_mfma32 = NX == 3 && NR == 3;
+      continue;
+    }
+    use_mfma32 = g.kind == FEM_SRC_ARRAY;   // a view of the group's staged row
+    for (int x = 0; x < NX && use_mfma32; ++x)
+      for (int r = 0; r < NR && use_mfma32; ++r) {
+        const int64_t pos = g.off0 + x * g.s0[1] + r * g.s0[2];
+        use_mfma32 = pos >= 0 && pos < c.grp[0].g_row;
+      }
+  }
+  // S is read in place when it is dense [r][i][j]; other layouts are packed
+  // into that layout first (one small kernel, only when needed).
+  PackArgs pk;
+  pk.n_groups = c.n_groups;
+  pk.NR = NR;
+  pk.NI = NI;
+  pk.NJ = NJ;
+  bool need_pack = false;
+  pk.transposed = chunks_of(f64, NI, NR) == 1 ? 1 : 0;
+  for (int k = 0; k < c.n_groups; ++k) {
+    FemGroup &G = c.grp[k];
+    const bool dense = !pk.transposed && G.ss[2] == 1 && (NI == 1 || G.ss[1] == NJ) &&
+                       (NR == 1 || G.ss[0] == (int64_t)NI * NJ);
+    G.s_dense = dense ? 1 : 0;
+    pk.S[k] = dense ? nullptr : G.S;
+    pk.sr[k] = G.ss[0];
+    pk.si[k] = G.ss[1];
+    pk.sj[k] = G.ss[2];
+    // the matrix-core variant reads S in place; a partial last tile still
+    // goes to the general kernel, which reads the packed layout
+    need_pack |= !dense && !(use_mfma32 && full_tiles == tiles);
+  }
+  hipError_t e = hipSuccess;
+  if (need_pack) {
+    const int pack_total = NR * NI * NJ * c.n_groups;
+    dim3 pgrid((pack_total + 255) / 256);
+    if (f64)
+      hipLaunchKernelGGL(pack_s_kernel<double>, pgrid, dim3(256), 0, stream, pk,
+                         (double *)workspace);
+    else
+      hipLaunchKernelGGL(pack_s_kernel<float>, pgrid, dim3(256), 0, stream, pk,
+                         (float *)workspace);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (blocks_per_cu < 1) blocks_per_cu = 1;
   const int64_t cap = (int64_t)device_cu_count() * blocks_per_cu;
   auto launch = [&](bool fast, int64_t t0, int64_t t1) -> hipError_t {
     FemArgs d = c;
@@ -1656,7 +1863,7 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
                c.grp[g].ss[1] == c.grp[0].ss[1] && c.grp[g].ss[2] == c.grp[0].ss[2];
   // Lean variant: one group, one output component per member, G absent or
   // one shared row of plain views.
-  bool use_lean = variant != 1 && !use_mfma && fast_ok && full_tiles > 0 && NX == 1 && !ew &&
+  bool use_lean = variant != 1 && !use_mfma && !use_mfma32 && fast_ok && full_tiles > 0 && NX == 1 && !ew &&
                   c.n_groups == 1 &&
                   pk.transposed && c.n_members <= 3 && c.grp[0].m0 == 0 &&
                   c.grp[0].m1 == c.n_members && lean_shape(f64, NI, NJ, NR);
@@ -1693,7 +1900,20 @@ hipError_t launch_fem(bool f64, int NI, int NJ, int NR, int NX, const FemArgs &a
     }
   }
   if (ev_start && (e = hipEventRecord(ev_start, stream)) != hipSuccess) return e;
-  if (use_lean) {
+  if (use_mfma32) {
+    const int64_t units = full_tiles * (kTile / 16);
+    const int64_t blocks = std::min<int64_t>((units + kMW32 - 1) / kMW32,
+                                             (int64_t)device_cu_count() * blocks_per_cu);
+    FemArgs d = c;
+    d.tile0 = 0;
+    d.tile1 = full_tiles;
+    e = hipErrorInvalidValue;
+#define BES_FEM_MFMA32_DISPATCH(ni, nj, nr, nx)                                           \
+    if (NI == ni && NJ == nj && NR == nr && NX == nx) e = launch_mfma32_shape<ni, nj, nr, nx>(d, (int)blocks, stream);
+    BES_FEM_SHAPES(BES_FEM_MFMA32_DISPATCH)
+#undef BES_FEM_MFMA32_DISPATCH
+    if (e != hipSuccess) return e;
+  } else if (use_lean) {
     const int wpt = variant == 2 ? 1 : 2;       // waves per tile
     dim3 lgrid((unsigned)std::min<int64_t>(full_tiles, cap));
     e = hipErrorInvalidValue;

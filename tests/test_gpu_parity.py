@@ -85,39 +85,74 @@ def test_config2_full_size(ctx, dtype):
     _check_sampled(p, w)
 
 
-def test_config2_full_size_whole_output_every_candidate(ctx):
-    """The P3 gradient batch at full size (e = 2^20, FP64), every output
-    element against the oracle, in every FEM-stream configuration the tuner
-    may record for it (the launch the benchmark times is one of them)."""
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_config2_full_size_whole_output_every_candidate(ctx, dtype):
+    """The P3 gradient batch at full size (e = 2^20), every output element
+    against the oracle, in every FEM-stream configuration the tuner may
+    record for it (the launch the benchmark times is one of them)."""
     from paper_2601_12220_amd import tune
-    w = workloads.config2(dtype="float64")
+    w = workloads.config2(dtype=dtype)
     p = ctx.register(w.notation, w.table, w.operands)
     assert p.template == "fem_stream"
     bufs = device_buffers(w)
     ref = oracle_full(w)
-    outs = [torch.empty(w.out_shape(), dtype=torch.float64, device="cuda") for _ in range(w.b)]
-    for cand in tune.candidates(capi.BES_T_FEM_STREAM):
-        _say(f"[parity-full] {w.name} config={cand}")
+    tdt = torch.float64 if dtype == "float64" else torch.float32
+    outs = [torch.empty(w.out_shape(), dtype=tdt, device="cuda") for _ in range(w.b)]
+    for cand in tune.candidates(capi.BES_T_FEM_STREAM, fp32=dtype == "float32"):
+        _say(f"[parity-full] {w.name} {dtype} config={cand}")
         for o in outs:
             o.fill_(float("nan"))
         p.set_config(*cand)
         p.launch(bufs, outs)
         torch.cuda.synchronize()
         for m in range(w.b):
-            err = rel_fro(outs[m].cpu().numpy(), ref[m])
-            assert err <= TOL["float64"], (cand, m, err)
+            err = rel_fro(outs[m].double().cpu().numpy(), ref[m])
+            assert err <= TOL[dtype], (cand, m, err)
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("bpc", [1, 64])
 def test_config2_kernel_variants(ctx, dtype, variant, bpc):
-    """The lean kernel with two waves per tile (variant 0) and one (2), and
-    the descriptor-driven one (1), on the P3 gradient batch with a ragged
-    tail; one block per CU makes every block walk several tiles."""
+    """The lean kernel with two waves per tile (variant 0) and one (2), the
+    descriptor-driven one (1) and the FP32 matrix-core one (3; FP64 falls
+    back to the lean kernel), on the P3 gradient batch with a ragged tail;
+    one block per CU makes every block walk several tiles."""
     w = workloads.config2(e=64 * 1093 + 29, dtype=dtype)
     p = ctx.register(w.notation, w.table, w.operands)
     p.set_config(capi.BES_T_FEM_STREAM, 64, bpc, variant)
+    _check_full(p, w)
+
+
+def _tet_one_member(ni, e, dt):
+    """'rij,exr,ej->exi' with one member: G the tetrahedron Jacobian of V,
+    u a plain array."""
+    bufs = {"V": workloads._uniform(12, 0, (e, 4, 3), 0.0, 1.0, dt),
+            "D": workloads._uniform(12, 1, (3, ni, ni), -1.0, 1.0, dt),
+            "u": workloads._normal(12, 2, (e, ni), dt)}
+    ops = {"D": workloads._dense("D", bufs["D"], dt), "u": workloads._dense("u", bufs["u"], dt),
+           "J": workloads.Operand("J", (e, 3, 3), dt, "tet_jacobian", ("V",))}
+    return workloads.Workload(f"tet_one_p{ni}", "rij,exr,ej->exi", [["D", "J", "u"]], ops, bufs,
+                              dt, {"e": e, "ni": ni})
+
+
+@pytest.mark.parametrize("case", ["p3_views", "p4_views", "p2_views", "p1_views", "p4_tet",
+                                  "p2_tet"])
+@pytest.mark.parametrize("bpc", [1, 64])
+def test_fp32_matrix_core_variant(ctx, case, bpc):
+    """The FP32 matrix-core variant (p[2] = 3): three members reading views
+    of one Jacobian row (the P3 gradient batch at P1..P4 extents) and one
+    member reading a tetrahedron Jacobian, ragged tails; one block per CU
+    makes every wave walk several 16-element units."""
+    e = 64 * 523 + 45
+    ni = {"p1": 4, "p2": 10, "p3": 20, "p4": 35}[case[:2]]
+    if case.endswith("views"):
+        w = workloads.config2(e=e, ni=ni, dtype="float32")
+    else:
+        w = _tet_one_member(ni, e, "float32")
+    p = ctx.register(w.notation, w.table, w.operands)
+    assert p.template == "fem_stream"
+    p.set_config(capi.BES_T_FEM_STREAM, 64, bpc, 3)
     _check_full(p, w)
 
 
@@ -138,7 +173,7 @@ def test_lean_kernel_one_member_and_without_g(ctx, dtype):
     for w in (one, no_g):
         p = ctx.register(w.notation, w.table, w.operands)
         assert p.template == "fem_stream"
-        for variant in (0, 1, 2):
+        for variant in (0, 1, 2, 3):
             p.set_config(capi.BES_T_FEM_STREAM, 64, 16, variant)
             _check_full(p, w)
 
@@ -186,13 +221,14 @@ def test_config3_matrix_core_mappings(ctx, variant, bpc):
 
 
 @pytest.mark.parametrize("nx", [3, 1])
-@pytest.mark.parametrize("variant", [0, 1])
-def test_p4_matrix_core_plain_operands(ctx, nx, variant):
+@pytest.mark.parametrize("variant,dt", [(0, "float64"), (1, "float64"), (3, "float32"),
+                                        (0, "float32")])
+def test_p4_matrix_core_plain_operands(ctx, nx, variant, dt):
     """P4 gradient batches whose operands are plain arrays (no element-wise
-    prologue), with G[e, x, r] and with G[e, r] (x absent), on both
-    matrix-core mappings, ragged tail."""
+    prologue), with G[e, x, r] and with G[e, r] (x absent): FP64 on both
+    matrix-core mappings, FP32 on its matrix-core variant (3) and on the
+    default path; ragged tail."""
     e = 64 * 301 + 17
-    dt = "float64"
     gshape = (e, 3, 3) if nx == 3 else (e, 3)
     bufs = {"D": workloads._uniform(11, 0, (3, 35, 35), -1.0, 1.0, dt),
             "G": workloads._normal(11, 1, gshape, dt)}

@@ -456,9 +456,9 @@ def test_fem_config_validation(ctx):
     tile), 1 (descriptor-driven) or 2 (lean, one wave per tile)."""
     w = workloads.config2(e=1000)
     p = ctx.register(w.notation, w.table, w.operands)
-    for good in ((64, 1, 0), (64, 64, 1), (64, 8, 2)):
+    for good in ((64, 1, 0), (64, 64, 1), (64, 8, 2), (64, 8, 3)):
         p.set_config(capi.BES_T_FEM_STREAM, *good)
-    for bad in ((64, 65, 0), (64, -1, 0), (64, 16, 3), (64, 16, -1)):
+    for bad in ((64, 65, 0), (64, -1, 0), (64, 16, 4), (64, 16, -1)):
         with pytest.raises(capi.BesError):
             p.set_config(capi.BES_T_FEM_STREAM, *bad)
 
