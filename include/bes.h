@@ -122,7 +122,10 @@ enum bes_template {
                             cores (other batches as 0); for the face-mass /
                             divergence class p[1] = blocks of four waves
                             per compute unit, p[2] = 0 or 1 the shared
-                            matrix in LDS, 2 as scalar operands */
+                            matrix in LDS, 2 as scalar operands, 3 (FP64,
+                            plain streamed operand with contiguous element
+                            rows) the shared-matrix product on the matrix
+                            cores */
   BES_T_GENERIC = 2,     /* any batched einsum; p[0] = outputs per tile,
                             p[1] = lanes per output (1,2,4,...,64),
                             p[2] = chunks of the shared contracted index

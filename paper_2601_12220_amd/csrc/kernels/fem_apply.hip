@@ -224,6 +224,208 @@ hipError_t launch_apply_shape(const FemApplyArgs &a, const T *Sp, int blocks_per
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// FP64 matrix-core variant (plain U): out[i, e] = sum_k S[i, k] W[k, e] with
+// k = (c, j) runs as v_mfma_f64_16x16x4f64 blocks, M = 16 values of i, N = 16
+// elements, K = 4 values of k; lane group q' = lane / 16 of the K side takes
+// k in [q' KQ, (q' + 1) KQ).  S sits in LDS once per block as A fragments.
+// Per unit of 16 elements a wave stages the geometry terms G[x, c, e] (once
+// per unit, shared by the members) and, per member, U's NP planes (each a
+// contiguous block of 16 x NJ values) through its LDS area with 16-byte
+// loads, forms W[k][n] there (one value per lane and pass, all 64 lanes
+// busy), reads its B fragments, runs the MB x KQ matrix instructions and
+// writes the unit's output block [n][i] through LDS.  A partial last unit
+// takes guarded scalar accesses.
+// ---------------------------------------------------------------------------
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+template <int NI, int NJ, int NC, int NX, bool DIAG>
+struct ApplyMfma {
+  static constexpr int kU = 16;                            // elements per unit
+  static constexpr int kNP = DIAG ? NC : NX;               // planes of U
+  static constexpr int kNG = DIAG ? NC : NX * NC;          // geometry values per element
+  static constexpr int kK = NC * NJ;                       // contracted (c, j)
+  static constexpr int kKQ = (kK + 3) / 4;                 // K blocks
+  static constexpr int kMB = (NI + 15) / 16;               // 16-row M blocks
+  static constexpr int kFrags = kMB * kKQ;
+  static constexpr int kUB = kU * NJ;                      // values of one plane block
+  static constexpr int kUArea = kNP * kUB;                 // >= kU * kK
+  static constexpr int kArea1 = kUArea > kU * kK ? kUArea : kU * kK;   // U, then W
+  static constexpr int kArea0 = kArea1 > kU * NI ? kArea1 : kU * NI;     // then out
+  static constexpr int kArea = (kArea0 + 1) & ~1;          // 16-byte multiple
+  static constexpr int kGArea = kNG * kU;
+  static constexpr int kPerWave = kArea + ((kGArea + 1) & ~1);
+  static constexpr int kLdsMax = 160 * 1024;
+  static constexpr int kW0 = (kLdsMax - kFrags * 64 * 8) / (kPerWave * 8);
+  static constexpr int kWaves = kW0 >= 8 ? 8 : (kW0 >= 4 ? 4 : (kW0 >= 2 ? 2 : 1));
+  static constexpr int kWT = (kU * kK + 63) / 64;          // W values per lane
+};
+
+template <int NI, int NJ, int NC, int NX, bool DIAG>
+__global__ void __launch_bounds__(512)
+    fem_apply_mfma_kernel(const FemApplyArgs a, int64_t n_units) {
+  using M = ApplyMfma<NI, NJ, NC, NX, DIAG>;
+  __shared__ double Sf[M::kFrags * 64];
+  __shared__ d2v Area2[M::kWaves * M::kPerWave / 2];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  double *const X = (double *)Area2 + wave * M::kPerWave;    // U planes, then W, then out
+  d2v *const XV = Area2 + wave * (M::kPerWave / 2);
+  double *const Gl = X + M::kArea;                            // [g][n]
+  // S as A fragments: fragment (mb, kb), lane l holds S[i][k] for
+  // i = 16 mb + l % 16 and k = (l / 16) KQ + kb, k = (c, j).
+  {
+    const double *__restrict__ S = (const double *)a.S;
+    for (int f = threadIdx.x; f < M::kFrags * 64; f += 64 * M::kWaves) {
+      const int frag = f >> 6, l = f & 63;
+      const int mb = frag / M::kKQ, kb = frag - mb * M::kKQ;
+      const int i = 16 * mb + (l & 15), k = (l >> 4) * M::kKQ + kb;
+      const int c = k / NJ, j = k - c * NJ;
+      Sf[f] = (i < NI && k < M::kK) ? S[c * a.ss[0] + i * a.ss[1] + j * a.ss[2]] : 0.0;
+    }
+    __syncthreads();
+  }
+  const int n = lane & 15, q = lane >> 4;
+  const double *__restrict__ Gp = (const double *)a.G;
+  for (int64_t un = (int64_t)blockIdx.x * M::kWaves + wave; un < n_units;
+       un += (int64_t)gridDim.x * M::kWaves) {
+    const int64_t e0 = un * M::kU;
+    const int n_el = (int)min((int64_t)M::kU, a.E - e0);
+    const bool full = n_el == M::kU;
+    // ---- geometry terms of the unit's elements: Gl[g][n] -------------------
+#pragma unroll
+    for (int t = 0; t < (M::kGArea + 63) / 64; ++t) {
+      const int f = lane + 64 * t;
+      const int g = f >> 4, el = f & 15;
+      if (f < M::kGArea) {
+        const int x = DIAG ? 0 : g / NC, c = DIAG ? g : g - (g / NC) * NC;
+        Gl[f] = el < n_el ? Gp[x * a.gs[0] + c * a.gs[1] + (e0 + el) * a.gs[2]] : 0.0;
+      }
+    }
+    for (int m = 0; m < a.n_members; ++m) {
+      const FemApplyMember &Mb = a.mem[m];
+      const double *__restrict__ U0 = (const double *)Mb.u0 + Mb.uoff0 + e0 * NJ;
+      // ---- U planes into X[p][el * NJ + j] ---------------------------------
+      if (full) {
+#pragma unroll
+        for (int p = 0; p < M::kNP; ++p) {
+          const d2v *__restrict__ pu = (const d2v *)(U0 + p * Mb.us0[0]);
+#pragma unroll
+          for (int t = 0; t < (M::kUB / 2 + 63) / 64; ++t) {
+            const int qv = lane + 64 * t;
+            if ((t + 1) * 64 <= M::kUB / 2 || qv < M::kUB / 2)
+              XV[(p * M::kUB) / 2 + qv] = __builtin_nontemporal_load(&pu[qv]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < M::kNP; ++p)
+          for (int f = lane; f < M::kUB; f += 64)
+            X[p * M::kUB + f] = f < n_el * NJ ? U0[p * Mb.us0[0] + f] : 0.0;
+      }
+      wave_sync();
+      // ---- W[k][n] = sum_x G[x][c][n] U[x][n][j] (face mass: G[c][n] U[c][n][j])
+      double wv[M::kWT];
+#pragma unroll
+      for (int t = 0; t < M::kWT; ++t) {
+        const int f = lane + 64 * t;
+        const int k = f >> 4, el = f & 15;
+        const int c = k / NJ, j = k - c * NJ;
+        double w = 0.0;
+        if (f < M::kU * M::kK) {
+          if constexpr (DIAG) {
+            w = Gl[c * M::kU + el] * X[c * M::kUB + el * NJ + j];
+          } else {
+#pragma unroll
+            for (int x = 0; x < NX; ++x)
+              w = fma(Gl[(x * NC + c) * M::kU + el], X[x * M::kUB + el * NJ + j], w);
+          }
+        }
+        wv[t] = w;
+      }
+      wave_sync();
+#pragma unroll
+      for (int t = 0; t < M::kWT; ++t) {
+        const int f = lane + 64 * t;
+        if (f < M::kU * M::kK) X[f] = wv[t];
+      }
+      wave_sync();
+      double bf[M::kKQ];
+#pragma unroll
+      for (int kb = 0; kb < M::kKQ; ++kb) {
+        const int k = q * M::kKQ + kb;
+        bf[kb] = k < M::kK ? X[k * M::kU + n] : 0.0;
+      }
+      wave_sync();
+      // ---- out[i][n] on the matrix cores ----------------------------------
+      d4v acc[M::kMB];
+#pragma unroll
+      for (int mb = 0; mb < M::kMB; ++mb) acc[mb] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kb = 0; kb < M::kKQ; ++kb)
+#pragma unroll
+        for (int mb = 0; mb < M::kMB; ++mb)
+          acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Sf[(mb * M::kKQ + kb) * 64 + lane],
+                                                         bf[kb], acc[mb], 0, 0, 0);
+      // ---- output block: item v of block mb is i = 16 mb + 4 v + q --------
+      double *__restrict__ out = (double *)Mb.out;
+      if (full && Mb.oe == NI && Mb.oi == 1 && ((uintptr_t)out & 15) == 0) {
+#pragma unroll
+        for (int mb = 0; mb < M::kMB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * mb + 4 * v + q;
+            if (i < NI) X[n * NI + i] = acc[mb][v];
+          }
+        wave_sync();
+        d2v *__restrict__ ov = (d2v *)(out + e0 * NI);
+#pragma unroll
+        for (int t = 0; t < (M::kU * NI / 2 + 63) / 64; ++t) {
+          const int qv = lane + 64 * t;
+          if ((t + 1) * 64 <= M::kU * NI / 2 || qv < M::kU * NI / 2) {
+            const d2v vv = XV[qv];
+            __builtin_nontemporal_store(vv, &ov[qv]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int mb = 0; mb < M::kMB; ++mb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * mb + 4 * v + q;
+            if (i < NI && n < n_el) out[(e0 + n) * Mb.oe + i * Mb.oi] = acc[mb][v];
+          }
+      }
+      wave_sync();
+    }
+  }
+}
+
+// The matrix-core variant takes plain U whose element rows are contiguous
+// (j stride 1, element stride NJ) and 16-byte aligned per plane.
+bool apply_mfma_ok(const FemApplyArgs &a, int NJ) {
+  if (a.u_kind != FEM_SRC_ARRAY) return false;
+  for (int m = 0; m < a.n_members; ++m) {
+    const FemApplyMember &M = a.mem[m];
+    if (M.us0[2] != 1 || M.us0[1] != NJ || (M.us0[0] & 1)) return false;
+    if ((((uintptr_t)M.u0 + (uintptr_t)(M.uoff0 * 8)) & 15) != 0) return false;
+  }
+  return true;
+}
+
+template <int NI, int NJ, int NC, int NX, bool DIAG>
+hipError_t launch_apply_mfma_shape(const FemApplyArgs &a, int blocks_per_cu, hipStream_t stream) {
+  using M = ApplyMfma<NI, NJ, NC, NX, DIAG>;
+  const int64_t units = (a.E + M::kU - 1) / M::kU;
+  const int64_t cap = (int64_t)device_cu_count() * std::max(1, blocks_per_cu);
+  const int64_t blocks = std::min<int64_t>((units + M::kWaves - 1) / M::kWaves, cap);
+  hipLaunchKernelGGL((fem_apply_mfma_kernel<NI, NJ, NC, NX, DIAG>), dim3((unsigned)blocks),
+                     dim3(64 * M::kWaves), 0, stream, a, units);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 size_t fem_apply_workspace_bytes(bool f64, int NI, int NJ, int NC) {
@@ -236,8 +438,21 @@ hipError_t launch_fem_apply(bool f64, int NI, int NJ, int NC, int NX, bool diag,
                             hipEvent_t ev_stop) {
   if (a.E <= 0 || a.n_members <= 0) return hipSuccess;
   // variant 2: S as scalar operands; 0 and 1: S in LDS (measured faster on
-  // most shapes; the tuner picks per shape)
+  // most shapes; the tuner picks per shape); 3: S W on the FP64 matrix cores
   const bool sreg = variant == 2;
+  if (variant == 3 && f64 && apply_mfma_ok(a, NJ)) {
+    hipError_t em = hipSuccess;
+    if (ev_start && (em = hipEventRecord(ev_start, stream)) != hipSuccess) return em;
+    em = hipErrorInvalidValue;
+#define BES_APPLY_MFMA_DISPATCH(ni, nj, nc, nx, dg)                                          \
+    if (NI == ni && NJ == nj && NC == nc && NX == nx && diag == dg)                          \
+      em = launch_apply_mfma_shape<ni, nj, nc, nx, dg>(a, blocks_per_cu, stream);
+    BES_FEM_APPLY_SHAPES(BES_APPLY_MFMA_DISPATCH)
+#undef BES_APPLY_MFMA_DISPATCH
+    if (em != hipSuccess) return em;
+    if (ev_stop && (em = hipEventRecord(ev_stop, stream)) != hipSuccess) return em;
+    return hipSuccess;
+  }
   if (sreg && !workspace) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
   if (sreg) {

@@ -25,19 +25,19 @@ T_MFMA = 3
 T_GETT = 4
 
 
-def candidates(template_id: int, fp32: bool = False) -> List[Tuple[int, ...]]:
+def candidates(template_id: int) -> List[Tuple[int, ...]]:
     """Parameter tuples (template id first) the tuner tries for a template.
 
     FEM stream: p[1] = blocks per compute unit in the grid, p[2] = kernel
                 variant (0 lean with two waves per tile, 2 lean with one,
-                1 descriptor-driven, 3 FP32 matrix cores; FP32 plans only).
+                1 descriptor-driven, 3 matrix cores: FP32 gradient class,
+                FP64 face-mass / divergence class; as 0 elsewhere).
     Generic:    p[0] = outputs per tile, p[1] = lanes per output, p[2] = chunks
                 of the shared contracted space (their sums add into the output).
     MFMA:       the single 128 x 128 tile shape the template implements.
     GETT:       p[2] = K ranges per output tile, p[3] = tile shape."""
     if template_id == T_FEM_STREAM:
-        variants = (0, 2, 1, 3) if fp32 else (0, 2, 1)
-        return [(T_FEM_STREAM, 64, b, v) for v in variants for b in (4, 8, 16, 32, 64)]
+        return [(T_FEM_STREAM, 64, b, v) for v in (0, 2, 1, 3) for b in (4, 8, 16, 32, 64)]
     if template_id == T_GENERIC:
         # p[2]: chunks of the shared contracted space per output (1: none)
         return ([(T_GENERIC, tile, lanes, 1) for tile in (64, 256, 1024) for lanes in (1, 4, 16, 64)]
@@ -100,8 +100,7 @@ def tune(ctx, plan, buffers: Dict[str, object], outputs: Sequence[object], strea
         # side stream, after everything queued so far has finished
         torch.cuda.synchronize()
         stream = torch.cuda.Stream()
-    cands = candidates(plan.config.template_id,
-                       fp32=all(d == "f32" for d in plan.dtypes) and bool(plan.dtypes))
+    cands = candidates(plan.config.template_id)
     if not cands:
         return None
     src = plan.src_ptrs(buffers)

@@ -98,7 +98,7 @@ def test_config2_full_size_whole_output_every_candidate(ctx, dtype):
     ref = oracle_full(w)
     tdt = torch.float64 if dtype == "float64" else torch.float32
     outs = [torch.empty(w.out_shape(), dtype=tdt, device="cuda") for _ in range(w.b)]
-    for cand in tune.candidates(capi.BES_T_FEM_STREAM, fp32=dtype == "float32"):
+    for cand in tune.candidates(capi.BES_T_FEM_STREAM):
         _say(f"[parity-full] {w.name} {dtype} config={cand}")
         for o in outs:
             o.fill_(float("nan"))
