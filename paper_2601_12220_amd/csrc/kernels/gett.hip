@@ -275,12 +275,13 @@ hipError_t launch_tile(const GettArgs &args, int ksplit, hipStream_t stream) {
   const int64_t base = tm * tn * a.n_slots;
   const int64_t ktot = (a.K + TL::BK - 1) / TL::BK;
   // Split K when the output tiles alone cannot fill the chip: enough ranges
-  // for about two blocks per compute unit, each at least sixteen K stages
-  // (every range adds its partial tile atomically, and many ranges per
-  // output contend on the same addresses).
+  // for about four blocks per compute unit, each at least eight K stages
+  // (every range adds its partial tile atomically).  Skinny contractions
+  // (a few dozen outputs along M or N, K in the tens of thousands) need
+  // hundreds of ranges to stream their operands at full rate.
   if (ksplit <= 0) {
-    const int64_t want = (2 * (int64_t)device_cu_count() + base - 1) / base;
-    ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, ktot / 16, 64}));
+    const int64_t want = (4 * (int64_t)device_cu_count() + base - 1) / base;
+    ksplit = (int)std::max<int64_t>(1, std::min<int64_t>({want, ktot / 8, 1024}));
   }
   a.ksplit = std::max(1, std::min<int>(ksplit, (int)std::max<int64_t>(ktot, 1)));
   const int64_t blocks = base * a.ksplit;

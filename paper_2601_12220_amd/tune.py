@@ -45,8 +45,8 @@ def candidates(template_id: int) -> List[Tuple[int, ...]]:
     if template_id == T_MFMA:
         return [(T_MFMA, 128, 128)]
     if template_id == T_GETT:   # p[2]: K ranges per tile (0: launcher's), p[3]: tile shape
-        return ([(T_GETT, 64, 64, ks, 0) for ks in (0, 1, 4, 16, 64)] +
-                [(T_GETT, 64, 64, 0, sh) for sh in (1, 2, 3, 4, 5)])
+        return ([(T_GETT, 64, 64, ks, 0) for ks in (0, 1, 4, 16, 64, 256)] +
+                [(T_GETT, 64, 64, ks, sh) for sh in (1, 2, 3, 4, 5) for ks in (0, 256)])
     return []
 
 
