@@ -304,11 +304,39 @@ __global__ void __launch_bounds__(512)
         Gl[f] = el < n_el ? Gp[x * a.gs[0] + c * a.gs[1] + (e0 + el) * a.gs[2]] : 0.0;
       }
     }
+    // U planes of the next member of the unit, loaded into registers while
+    // the current member computes (shapes whose planes take at most eight
+    // 16-byte values per lane)
+    constexpr int kUT = (M::kUB / 2 + 63) / 64;
+    constexpr bool PF = M::kNP * kUT <= 8;
+    d2v pre[PF ? M::kNP : 1][PF ? kUT : 1];
+    auto load_planes = [&](const FemApplyMember &Mn, d2v (&dst)[PF ? M::kNP : 1][PF ? kUT : 1]) {
+      const double *__restrict__ Un = (const double *)Mn.u0 + Mn.uoff0 + e0 * NJ;
+#pragma unroll
+      for (int p = 0; p < (PF ? M::kNP : 1); ++p) {
+        const d2v *__restrict__ pu = (const d2v *)(Un + p * Mn.us0[0]);
+#pragma unroll
+        for (int t = 0; t < (PF ? kUT : 1); ++t) {
+          int qv = lane + 64 * t;
+          if ((t + 1) * 64 > M::kUB / 2) qv = qv < M::kUB / 2 ? qv : M::kUB / 2 - 1;
+          dst[p][t] = __builtin_nontemporal_load(&pu[qv]);
+        }
+      }
+    };
+    bool have_pre = false;
     for (int m = 0; m < a.n_members; ++m) {
       const FemApplyMember &Mb = a.mem[m];
       const double *__restrict__ U0 = (const double *)Mb.u0 + Mb.uoff0 + e0 * NJ;
       // ---- U planes into X[p][el * NJ + j] ---------------------------------
-      if (full) {
+      if (full && PF && have_pre) {
+#pragma unroll
+        for (int p = 0; p < (PF ? M::kNP : 1); ++p)
+#pragma unroll
+          for (int t = 0; t < (PF ? kUT : 1); ++t) {
+            const int qv = lane + 64 * t;
+            if ((t + 1) * 64 <= M::kUB / 2 || qv < M::kUB / 2) XV[(p * M::kUB) / 2 + qv] = pre[p][t];
+          }
+      } else if (full) {
 #pragma unroll
         for (int p = 0; p < M::kNP; ++p) {
           const d2v *__restrict__ pu = (const d2v *)(U0 + p * Mb.us0[0]);
@@ -326,6 +354,13 @@ __global__ void __launch_bounds__(512)
             X[p * M::kUB + f] = f < n_el * NJ ? U0[p * Mb.us0[0] + f] : 0.0;
       }
       wave_sync();
+      have_pre = false;
+      if constexpr (PF) {
+        if (full && m + 1 < a.n_members) {
+          load_planes(a.mem[m + 1], pre);
+          have_pre = true;
+        }
+      }
       // ---- W[k][n] = sum_x G[x][c][n] U[x][n][j] (face mass: G[c][n] U[c][n][j])
       double wv[M::kWT];
 #pragma unroll
