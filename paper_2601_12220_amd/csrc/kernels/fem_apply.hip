@@ -305,10 +305,10 @@ __global__ void __launch_bounds__(512)
       }
     }
     // U planes of the next member of the unit, loaded into registers while
-    // the current member computes (shapes whose planes take at most eight
+    // the current member computes (shapes whose planes take at most twelve
     // 16-byte values per lane)
     constexpr int kUT = (M::kUB / 2 + 63) / 64;
-    constexpr bool PF = M::kNP * kUT <= 8;
+    constexpr bool PF = M::kNP * kUT <= 12;
     d2v pre[PF ? M::kNP : 1][PF ? kUT : 1];
     auto load_planes = [&](const FemApplyMember &Mn, d2v (&dst)[PF ? M::kNP : 1][PF ? kUT : 1]) {
       const double *__restrict__ Un = (const double *)Mn.u0 + Mn.uoff0 + e0 * NJ;
