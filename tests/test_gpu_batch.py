@@ -165,7 +165,10 @@ def test_benched_256_batch_matches_oracle_and_plain(benched_batch):
             worst = max(worst, eb)
             assert eb <= TOL["float32"], (k, w.notation, m, eb, plans[k].config.p[:3])
             assert rel_fro(got_p, refs[k][m]) <= TOL["float32"], (k, w.notation, m)
-            assert rel_fro(got_b, got_p) <= TOL["float32"], (k, m)
+            # both are within the FP32 bound of the oracle; split einsums add
+            # their chunks atomically in a run-dependent order, so the two
+            # FP32 results differ by up to twice that bound
+            assert rel_fro(got_b, got_p) <= 2 * TOL["float32"], (k, m)
     _say(f"[batch256] worst relative Frobenius error vs oracle {worst:.3e}")
 
 
