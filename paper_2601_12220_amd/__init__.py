@@ -147,15 +147,6 @@ class Plan:
     def canonical(self) -> str:
         return capi.bes_plan_canonical(self.h)
 
-    @property
-    def dtypes(self) -> List[str]:
-        """Element types of the canonical operands ("f64", "f32", ...), as the
-        key states them."""
-        for part in self.key.split(";"):
-            if part.startswith("dt="):
-                return part[3:].split(",")
-        return []
-
     def maps(self):
         """(member_map, pos_map, arg_map as names, index_map) from canonical
         names to this registration's names."""
