@@ -268,7 +268,7 @@ def run_fem(w, min_s, tune_first=True):
            "gbs": nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes, "bytes_read": rd,
            "bytes_written": wr,
            "template": plan.template, "register_us": reg, "key": plan.key,
-           "config": [cfg.template_id] + [int(cfg.p[k]) for k in range(4)], "tuned": tuned}
+           "config": [cfg.template_id] + [int(cfg.p[k]) for k in range(5)], "tuned": tuned}
     fl = fem_flops(w)
     if fl:
         res["tflops"] = fl / (ms * 1e-3) / 1e12

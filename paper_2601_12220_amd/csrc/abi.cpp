@@ -290,6 +290,7 @@ void bes_plan_destroy(bes_plan *plan) {
   if (!plan) return;
   free_gen_cache(plan->p);
   if (plan->p.fem_ws) (void)hipFree(plan->p.fem_ws);
+  if (plan->p.gett_ws) (void)hipFree(plan->p.gett_ws);
   delete plan;
 }
 
@@ -506,8 +507,35 @@ int bes_launch(const bes_plan *plan, const void *const *src_ptrs, void *const *o
       GettArgs a = gc->args;
       a.tab = gc->dev;
       bes::bind_gett_ptrs(p, src.data(), out_ptrs, a);
+      // partial tiles of a K split: up to 1024 ranges of every output, at
+      // most 64 MiB (larger outputs split little and add atomically)
+      {
+        int dev = 0;
+        if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (p.gett_ws && p.gett_ws_device != dev) {
+          (void)hipFree(p.gett_ws);
+          p.gett_ws = nullptr;
+        }
+        if (!p.gett_ws && p.cfg.p[4] == 1) {
+          const size_t esz = f64 ? 8 : 4;
+          const size_t one = (size_t)a.M * (size_t)a.N * (size_t)a.n_slots * esz;
+          const size_t bytes = std::min<size_t>(one * 1024, (size_t)64 << 20);
+          if (bytes >= one * 4) {
+            if ((e = hipMalloc(&p.gett_ws, bytes)) != hipSuccess) {
+              p.gett_ws = nullptr;
+              return hip_fail(e, "GETT workspace allocation");
+            }
+            p.gett_ws_bytes = bytes;
+            p.gett_ws_device = dev;
+          }
+        }
+      }
       if ((e = record(p.time_start)) != hipSuccess) return hip_fail(e, "timing event");
-      e = bes::launch_gett(f64, a, p.cfg.p[3], p.cfg.p[2], stream);
+      // p[4] = 1: a K split of eight or more ranges sums its partial tiles in
+      // a second kernel (else they add atomically)
+      const bool two_pass = p.cfg.p[4] == 1 && p.gett_ws;
+      e = bes::launch_gett(f64, a, p.cfg.p[3], p.cfg.p[2], two_pass ? p.gett_ws : nullptr,
+                           two_pass ? p.gett_ws_bytes : 0, stream);
       if (e != hipSuccess) return hip_fail(e, "GETT launch");
       if ((e = record(p.time_stop)) != hipSuccess) return hip_fail(e, "timing event");
       return BES_OK;

@@ -252,8 +252,10 @@ typedef struct GettArgs {
   const int64_t *tab;               // device offset tables
   int32_t n_members, n_slots;
   int32_t ksplit;                   // K ranges per output tile (> 1: partial
-                                    // tiles add atomically into C)
+                                    // tiles add atomically into C, or go to
+                                    // `partial` and a second kernel sums them)
   int32_t pad;
+  void *partial;                    // [ksplit][n_slots][M][N] partial tiles, or NULL
   GettMember mem[BES_GETT_MAX_B];
   GettSlot slot[BES_GETT_MAX_B];
 } GettArgs;

@@ -106,6 +106,11 @@ struct Plan {
   // FEM-stream workspace for the packed shared operand (first FEM launch).
   mutable void *fem_ws = nullptr;
   mutable int fem_ws_device = -1;
+  // GETT workspace for the partial tiles of a K-split launch (first GETT
+  // launch; fixed size, never regrown while launches may read it).
+  mutable void *gett_ws = nullptr;
+  mutable size_t gett_ws_bytes = 0;
+  mutable int gett_ws_device = -1;
   // Generic descriptors bound so far, one per (config, output layouts,
   // device): a pinned host copy and the device copy uploaded from it.  Kept
   // until the plan is destroyed, so a launch never waits for or frees a

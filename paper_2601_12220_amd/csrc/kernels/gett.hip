@@ -88,6 +88,23 @@ __global__ void __launch_bounds__(kThreads) gett_zero_kernel(const GettArgs a) {
   }
 }
 
+// Sum of the K ranges' partial tiles into C (overwriting, or adding into an
+// accumulating slot); grid-stride over (slot, m, n).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) gett_reduce_kernel(const GettArgs a) {
+  const int64_t per = a.M * a.N, total = per * a.n_slots;
+  const T *__restrict__ part = (const T *)a.partial;
+  for (int64_t f = blockIdx.x * (int64_t)kThreads + threadIdx.x; f < total;
+       f += (int64_t)gridDim.x * kThreads) {
+    const int sl = (int)(f / per);
+    const int64_t r = f - sl * per, m = r / a.N, n = r - m * a.N;
+    T sum = 0;
+    for (int k = 0; k < a.ksplit; ++k) sum += part[(int64_t)k * total + f];
+    T *p = (T *)a.slot[sl].C + a.tab[a.slot[sl].rowC + m] + a.tab[a.slot[sl].colC + n];
+    *p = a.slot[sl].acc ? *p + sum : sum;
+  }
+}
+
 // Tile shapes: BM x BN outputs per block of four waves laid out WM x WN,
 // each wave 16 TI x 16 TJ; K staged BK deep.  The skinny shapes serve
 // contractions with few rows or columns (TCCG-like cases often have one
@@ -261,6 +278,10 @@ __global__ void __launch_bounds__(kThreads) gett_kernel(const GettArgs a, int ti
       for (int v = 0; v < 4; ++v) {
         const int64_t m = m0 + (wm * TI + i) * 16 + MC::row(v, lane);
         if (m >= M) continue;
+        if (a.partial) {          // K split, summed by gett_reduce_kernel
+          ((T *)a.partial)[((int64_t)ks * a.n_slots + sl) * M * N + m * N + n] = acc[i][j][v];
+          continue;
+        }
         T *p = C + rowC[m] + cn;
         if (a.ksplit > 1) atomicAdd(p, acc[i][j][v]);   // into zeroed or caller's C
         else *p = S.acc ? *p + acc[i][j][v] : acc[i][j][v];
@@ -269,8 +290,10 @@ __global__ void __launch_bounds__(kThreads) gett_kernel(const GettArgs a, int ti
 }
 
 template <typename T, typename TL>
-hipError_t launch_tile(const GettArgs &args, int ksplit, hipStream_t stream) {
+hipError_t launch_tile(const GettArgs &args, int ksplit, void *ws, size_t ws_bytes,
+                       hipStream_t stream) {
   GettArgs a = args;
+  a.partial = nullptr;
   const int64_t tm = (a.M + TL::BM - 1) / TL::BM, tn = (a.N + TL::BN - 1) / TL::BN;
   const int64_t base = tm * tn * a.n_slots;
   const int64_t ktot = (a.K + TL::BK - 1) / TL::BK;
@@ -286,37 +309,47 @@ hipError_t launch_tile(const GettArgs &args, int ksplit, hipStream_t stream) {
   a.ksplit = std::max(1, std::min<int>(ksplit, (int)std::max<int64_t>(ktot, 1)));
   const int64_t blocks = base * a.ksplit;
   if (tm * tn > (1 << 24) || blocks > 0x7fffffff) return hipErrorInvalidValue;
-  if (a.ksplit > 1) {
-    const int64_t n = a.M * a.N * a.n_slots;
-    const unsigned g = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 8192);
+  const int64_t n = a.M * a.N * a.n_slots;
+  const unsigned g = (unsigned)std::min<int64_t>((n + kThreads - 1) / kThreads, 8192);
+  // Many ranges of few outputs: partial tiles to the workspace and a second
+  // kernel sums them (atomic adds of hundreds of ranges into the same few
+  // addresses serialize); otherwise they add atomically into the output.
+  if (a.ksplit >= 8 && ws && (size_t)a.ksplit * (size_t)n * sizeof(T) <= ws_bytes)
+    a.partial = ws;
+  if (a.ksplit > 1 && !a.partial)
     hipLaunchKernelGGL(gett_zero_kernel<T>, dim3(g), dim3(kThreads), 0, stream, a);
-  }
   hipLaunchKernelGGL((gett_kernel<T, TL>), dim3((unsigned)blocks), dim3(kThreads), 0, stream, a,
                      (int)tm, (int)tn);
+  if (a.partial) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gett_reduce_kernel<T>, dim3(g), dim3(kThreads), 0, stream, a);
+  }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_shape(const GettArgs &a, int shape, int ksplit, hipStream_t stream) {
+hipError_t launch_shape(const GettArgs &a, int shape, int ksplit, void *ws, size_t wsb,
+                        hipStream_t stream) {
   switch (shape) {
-    case 1: return launch_tile<T, Tile<16, 128, 16, 1>>(a, ksplit, stream);
-    case 2: return launch_tile<T, Tile<32, 128, 8, 1>>(a, ksplit, stream);
-    case 3: return launch_tile<T, Tile<128, 32, 8, 4>>(a, ksplit, stream);
-    case 4: return launch_tile<T, Tile<128, 16, 16, 4>>(a, ksplit, stream);
-    default: return launch_tile<T, Tile<kBM0, kBN0, kBK0, 2>>(a, ksplit, stream);
+    case 1: return launch_tile<T, Tile<16, 128, 16, 1>>(a, ksplit, ws, wsb, stream);
+    case 2: return launch_tile<T, Tile<32, 128, 8, 1>>(a, ksplit, ws, wsb, stream);
+    case 3: return launch_tile<T, Tile<128, 32, 8, 4>>(a, ksplit, ws, wsb, stream);
+    case 4: return launch_tile<T, Tile<128, 16, 16, 4>>(a, ksplit, ws, wsb, stream);
+    default: return launch_tile<T, Tile<kBM0, kBN0, kBK0, 2>>(a, ksplit, ws, wsb, stream);
   }
 }
 
 }  // namespace
 
-hipError_t launch_gett(bool f64, const GettArgs &a, int shape, int ksplit,
-                       hipStream_t stream) {
+hipError_t launch_gett(bool f64, const GettArgs &a, int shape, int ksplit, void *workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
   if (a.M <= 0 || a.N <= 0 || a.n_slots <= 0) return hipSuccess;
   // shape 0: by the output's extents -- skinny tiles for few rows or columns
   if (shape <= 0)
     shape = a.M <= 16 ? 1 : a.M <= 32 ? 2 : a.N <= 16 ? 4 : a.N <= 32 ? 3 : 5;
-  return f64 ? launch_shape<double>(a, shape, ksplit, stream)
-             : launch_shape<float>(a, shape, ksplit, stream);
+  return f64 ? launch_shape<double>(a, shape, ksplit, workspace, workspace_bytes, stream)
+             : launch_shape<float>(a, shape, ksplit, workspace, workspace_bytes, stream);
 }
 
 }  // namespace bes

@@ -62,7 +62,8 @@ hipError_t launch_fill_zero(void *p, int64_t n, int elem_bytes, hipStream_t stre
 // extents).  `ksplit` = K ranges per output tile (0: chosen from the tile
 // count and K; > 1 zeroes the overwritten outputs first, then adds partial
 // tiles atomically).
-hipError_t launch_gett(bool f64, const GettArgs &a, int shape, int ksplit, hipStream_t stream);
+hipError_t launch_gett(bool f64, const GettArgs &a, int shape, int ksplit, void *workspace,
+                       size_t workspace_bytes, hipStream_t stream);
 
 // MFMA dense-contraction template (FP32).  mfma_args_ok: the shape and the
 // alignment of every operand fit the template's vector tile loads.

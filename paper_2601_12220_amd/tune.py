@@ -35,7 +35,8 @@ def candidates(template_id: int) -> List[Tuple[int, ...]]:
     Generic:    p[0] = outputs per tile, p[1] = lanes per output, p[2] = chunks
                 of the shared contracted space (their sums add into the output).
     MFMA:       the single 128 x 128 tile shape the template implements.
-    GETT:       p[2] = K ranges per output tile, p[3] = tile shape."""
+    GETT:       p[2] = K ranges per output tile, p[3] = tile shape, p[4] = 1
+                partial tiles of >= 8 ranges summed by a second kernel."""
     if template_id == T_FEM_STREAM:
         return [(T_FEM_STREAM, 64, b, v) for v in (0, 2, 1, 3) for b in (4, 8, 16, 32, 64)]
     if template_id == T_GENERIC:
@@ -44,9 +45,11 @@ def candidates(template_id: int) -> List[Tuple[int, ...]]:
                 + [(T_GENERIC, 256, lanes, split) for lanes in (16, 64) for split in (8, 64)])
     if template_id == T_MFMA:
         return [(T_MFMA, 128, 128)]
-    if template_id == T_GETT:   # p[2]: K ranges per tile (0: launcher's), p[3]: tile shape
+    if template_id == T_GETT:   # p[2]: K ranges per tile (0: launcher's), p[3]: tile shape,
+        # p[4] = 1: partial tiles of >= 8 ranges summed by a second kernel
         return ([(T_GETT, 64, 64, ks, 0) for ks in (0, 1, 4, 16, 64, 256)] +
-                [(T_GETT, 64, 64, ks, sh) for sh in (1, 2, 3, 4, 5) for ks in (0, 256)])
+                [(T_GETT, 64, 64, ks, sh) for sh in (1, 2, 3, 4, 5) for ks in (0, 256)] +
+                [(T_GETT, 64, 64, ks, sh, 1) for sh in (0, 1, 2, 3, 4, 5) for ks in (64, 256)])
     return []
 
 

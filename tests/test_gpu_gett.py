@@ -126,3 +126,27 @@ def test_gett_every_tile_shape(ctx, shape, ksplit):
         plan = ctx.register(w.notation, w.table, w.operands)
         plan.set_config(T_GETT, 64, 64, ksplit, shape)
         _check(plan, w, TOL["float64"])
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5])
+def test_gett_many_k_ranges_summed_in_a_second_pass(ctx, shape):
+    """K split into 64 ranges (partial tiles to the workspace, summed by a
+    second kernel): two members summed per output, then the same plan
+    accumulating into a pre-filled output through a permuted layout; long
+    ragged K, every tile shape."""
+    w = _workload("ik,kj->ij", [["A1", "B"], ["A2", "B"]],
+                  {"A1": (100, 2011), "A2": (100, 2011), "B": (2011, 70)}, affine=("B",))
+    plan = ctx.register(w.notation, w.table, w.operands)
+    plan.set_config(T_GETT, 64, 64, 64, shape, 1)
+    _check(plan, w, TOL["float64"])
+    ref = oracle_full(w)
+    bufs = device_buffers(w)
+    pre = torch.randn(70, 100, dtype=torch.float64, device="cuda")   # stored [j][i]
+    out0 = pre.clone()
+    out1 = torch.empty(100, 70, dtype=torch.float64, device="cuda")
+    capi.bes_plan_set_output(plan.h, 0, 0, [1, 100], True)
+    plan.launch(bufs, [out0, out1])
+    torch.cuda.synchronize()
+    got = (out0 - pre).t().double().cpu().numpy()
+    assert rel_fro(got, ref[0]) <= TOL["float64"]
+    assert rel_fro(out1.double().cpu().numpy(), ref[1]) <= TOL["float64"]
