@@ -142,7 +142,8 @@ enum bes_template {
                             atomically into the zeroed output), p[3] =
                             tile shape (0: by the output's extents; 1: 16
                             x 128, 2: 32 x 128, 3: 128 x 32, 4: 128 x 16,
-                            5: 64 x 64), p[4] = 1: with eight or more K
+                            5: 64 x 64, 6: 64 x 64 with K staged 32 deep,
+                            7: 128 x 64), p[4] = 1: with eight or more K
                             ranges the partial tiles go to a plan-owned
                             workspace (allocated on the first such launch,
                             at most 64 MiB) and a second kernel sums them */

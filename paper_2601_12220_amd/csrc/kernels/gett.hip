@@ -11,9 +11,9 @@
 // the host), the affine map is applied in registers on the way to LDS, and
 // out-of-range elements of ragged edge tiles enter as exact zeros.
 //
-// Tiling: an output tile per block of four waves (64 x 64, or a skinny
-// 16 x 128, 32 x 128, 128 x 32 or 128 x 16 when the output has few rows or
-// columns), each wave a grid of 16 x 16 MFMA tiles, K staged 8 or 16 deep
+// Tiling: an output tile per block of four waves (64 x 64, 64 x 64 with K
+// staged 32 deep, 128 x 64, or a skinny 16 x 128, 32 x 128, 128 x 32 or
+// 128 x 16 when the output has few rows or columns), each wave a grid of 16 x 16 MFMA tiles, K staged 8 or 16 deep
 // through double-buffered LDS with register prefetch of the next stage.  FP64 runs v_mfma_f64_16x16x4f64,
 // FP32 v_mfma_f32_16x16x4f32.  Each operand's tile is read along whichever
 // of its two groups is contiguous in memory (host flag), so that neighbouring
@@ -336,6 +336,8 @@ hipError_t launch_shape(const GettArgs &a, int shape, int ksplit, void *ws, size
     case 2: return launch_tile<T, Tile<32, 128, 8, 1>>(a, ksplit, ws, wsb, stream);
     case 3: return launch_tile<T, Tile<128, 32, 8, 4>>(a, ksplit, ws, wsb, stream);
     case 4: return launch_tile<T, Tile<128, 16, 16, 4>>(a, ksplit, ws, wsb, stream);
+    case 6: return launch_tile<T, Tile<64, 64, 32, 2>>(a, ksplit, ws, wsb, stream);
+    case 7: return launch_tile<T, Tile<128, 64, 16, 2>>(a, ksplit, ws, wsb, stream);
     default: return launch_tile<T, Tile<kBM0, kBN0, kBK0, 2>>(a, ksplit, ws, wsb, stream);
   }
 }

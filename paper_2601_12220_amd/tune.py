@@ -48,7 +48,7 @@ def candidates(template_id: int) -> List[Tuple[int, ...]]:
     if template_id == T_GETT:   # p[2]: K ranges per tile (0: launcher's), p[3]: tile shape,
         # p[4] = 1: partial tiles of >= 8 ranges summed by a second kernel
         return ([(T_GETT, 64, 64, ks, 0) for ks in (0, 1, 4, 16, 64, 256)] +
-                [(T_GETT, 64, 64, ks, sh) for sh in (1, 2, 3, 4, 5) for ks in (0, 256)] +
+                [(T_GETT, 64, 64, ks, sh) for sh in (1, 2, 3, 4, 5, 6, 7) for ks in (0, 256)] +
                 [(T_GETT, 64, 64, ks, sh, 1) for sh in (0, 1, 2, 3, 4, 5) for ks in (64, 256)])
     return []
 

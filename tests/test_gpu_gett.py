@@ -115,7 +115,7 @@ def test_gett_full_size_stand_in_sampled(ctx, case):
     assert rel_fro(got, ref[0]) <= TOL["float64"]
 
 
-@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("ksplit", [1, 3])
 def test_gett_every_tile_shape(ctx, shape, ksplit):
     # each tile shape on ragged operands (rows and columns not multiples of
@@ -128,7 +128,7 @@ def test_gett_every_tile_shape(ctx, shape, ksplit):
         _check(plan, w, TOL["float64"])
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_gett_many_k_ranges_summed_in_a_second_pass(ctx, shape):
     """K split into 64 ranges (partial tiles to the workspace, summed by a
     second kernel): two members summed per output, then the same plan
