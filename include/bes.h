@@ -273,7 +273,13 @@ int bes_ctx_stats(const bes_ctx *ctx, int64_t *hits, int64_t *misses);
  *   out_ptrs: b device pointers of the outputs in user member order; output i
  *     is dense row-major with the extents of the output indices in the
  *     notation's order and is overwritten.
- * Asynchronous; returns BES_E_HIP if the launch could not be enqueued. */
+ * Asynchronous; returns BES_E_HIP if the launch could not be enqueued.
+ * The first launch of a plan on a device (and of a new config or output
+ * layout) allocates and uploads the plan's device state (descriptors, offset
+ * tables, workspaces); later launches of it only enqueue kernels, so a
+ * caller that captures launches in a HIP graph launches once before capture,
+ * or uses bes_launch_noalloc.  Launches of one plan that overlap in time on
+ * different streams share its workspaces and race. */
 int bes_launch(const bes_plan *plan, const void *const *src_ptrs,
                void *const *out_ptrs, void *hip_stream);
 
