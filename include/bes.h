@@ -332,8 +332,12 @@ int bes_plan_set_timing(bes_plan *plan, void *start_event, void *stop_event);
 
 /* Persistent batched launch of many plans (one kernel over a device work list
  * of (plan, member, tile) items, captured once in a hipGraph).
- * bes_batch_create uploads the descriptor table of every plan's current
- * config; bes_batch_launch binds pointers (src_ptrs[p], out_ptrs[p] as in
+ * bes_batch_create evaluates every plan with the generic template and picks
+ * its own decomposition per plan for the shared launch (lanes per output,
+ * chunks of the contracted space, outputs per work item, sized so that each
+ * work item reads about 128 values in sequence), since a plan's own config is
+ * tuned for a launch that has the device to itself; it uploads the descriptor
+ * table once.  bes_batch_launch binds pointers (src_ptrs[p], out_ptrs[p] as in
  * bes_launch for plan p) and replays.  Pointers may change between launches.
  * Set BES_NO_GRAPH=1 to launch without graph capture. */
 int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count,

@@ -667,6 +667,9 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
   std::vector<GenItem> items;
   std::vector<double> cost;
   std::string err;
+  // target serial chain of value reads per work-item (measured best between
+  // 64 and 128 on the 256-einsum batch; 32 and 256 are slower)
+  const double chain = 128.0;
   for (int k = 0; k < count; ++k) {
     if (!plans[k]) {
       bes_batch_destroy(B);
@@ -684,31 +687,51 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
       return fail(BES_E_UNSUPPORTED, "a batch must have one dtype");
     }
     bes_config c = p.cfg;
-    if (c.template_id != BES_T_GENERIC) {
-      c.template_id = BES_T_GENERIC;
-      c.p[0] = 256;
-      c.p[1] = 1;
-    }
+    c.template_id = BES_T_GENERIC;
+    c.p[0] = 256;
+    c.p[1] = 1;
+    c.p[2] = 1;
     int rc = bes::bind_generic_static(p, c, table[k], err);
     if (rc) {
       bes_batch_destroy(B);
       return fail(rc, err);
     }
     B->plans.push_back(&p);
-    const GenEinsum &g = table[k];
-    if (g.split > 1) B->any_split = true;
+    GenEinsum &g = table[k];
     if (!g.narrow) B->narrow = false;
-    // Work per output of the factored evaluation: the shared rows times the
-    // exclusive sums of the operands that depend on them, plus the others.
+    // Value reads per output: `rows` along the shared space (the row-dependent
+    // operands' exclusive sums at every shared row) and `once` for the other
+    // operands, which every lane of an output evaluates itself.
     double per = 0.0, once = 0.0;
     for (int op = 0; op < g.n_ops; ++op) {
       const double ex = (double)std::max<int64_t>(g.ex_size[op], 1);
       if ((g.row_dep >> op) & 1) per += ex;
       else once += ex;
     }
-    const int chunks = std::max(1, g.split);
-    const double per_output =
-        (double)std::max<int64_t>(g.sh_size, 1) * std::max(per, 1.0) / chunks + once;
+    const int64_t sh = std::max<int64_t>(g.sh_size, 1);
+    const double rows = (double)sh * std::max(per, 1.0);
+    // The einsum shares the machine with the others, so its decomposition is
+    // the batch's own (a plan's tuned config fills the whole device alone):
+    // lanes and chunks cut each work-item's serial chain of reads to about
+    // `chain`, lanes only while their redundant `once` reads stay below the
+    // useful ones, and a tile takes as many passes as fit in one chain.
+    int lanes = 1;
+    while (lanes < 64 && lanes * 2 <= sh && rows / (lanes * 2) >= chain * 0.5 &&
+           once * lanes * 2 <= rows)
+      lanes *= 2;
+    int chunks = 1;
+    while (chunks < 64 && (int64_t)lanes * chunks * 2 <= sh &&
+           rows / ((double)lanes * chunks) > 2.0 * chain)
+      chunks *= 2;
+    const double lane_chain = once + rows / ((double)lanes * chunks);
+    const int64_t per_pass = 256 / lanes;
+    const int64_t passes =
+        std::max<int64_t>(1, std::min<int64_t>((int64_t)(chain / lane_chain),
+                                               (g.out_size + per_pass - 1) / per_pass));
+    g.lanes = lanes;
+    g.split = chunks;
+    g.tile = (int32_t)(per_pass * passes);
+    if (g.split > 1) B->any_split = true;
     for (int s = 0; s < g.n_slots; ++s) {
       const int members = g.slot_m1[s] - g.slot_m0[s];
       for (int64_t f = 0; f < g.out_size; f += g.tile) {
@@ -721,7 +744,8 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
           it.count = std::min<int64_t>(g.tile, g.out_size - f);
           it.chunk = ch;
           items.push_back(it);
-          cost.push_back((double)it.count * members * per_output);
+          const int64_t np = (it.count + per_pass - 1) / per_pass;
+          cost.push_back((double)np * members * lane_chain);
         }
       }
     }

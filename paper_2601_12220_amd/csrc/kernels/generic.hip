@@ -46,11 +46,15 @@ __global__ void __launch_bounds__(256) zero_split_one(const GenEinsum *__restric
   zero_slots<T>(*G, P);
 }
 
-template <typename T, bool NARROW>
-__global__ void __launch_bounds__(256) persistent_kernel(const GenEinsum *__restrict__ table,
-                                                         const GenPtrs *__restrict__ ptrs,
-                                                         const GenItem *__restrict__ items,
-                                                         int n_items, unsigned *counters) {
+// W: minimum waves per SIMD the register allocation must allow.  The FP32
+// instantiations are held to 128 VGPRs (4 waves, one per resident block of
+// the persistent grid): their loop waits on loads and gains from the waves
+// more than it loses to a few spills outside it.  The FP64 ones would spill
+// heavily and keep the compiler's choice.
+template <typename T, bool NARROW, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W)))
+persistent_kernel(const GenEinsum *__restrict__ table, const GenPtrs *__restrict__ ptrs,
+                  const GenItem *__restrict__ items, int n_items, unsigned *counters) {
   __shared__ int item;
   for (;;) {
     if (threadIdx.x == 0) item = (int)atomicAdd(&counters[0], 1u);
@@ -132,16 +136,16 @@ hipError_t launch_persistent(bool f64, const GenEinsum *table, const GenPtrs *pt
                          table, ptrs);
   }
   if (f64 && narrow)
-    hipLaunchKernelGGL((persistent_kernel<double, true>), dim3(grid), dim3(256), 0, stream,
+    hipLaunchKernelGGL((persistent_kernel<double, true, 1>), dim3(grid), dim3(256), 0, stream,
                        table, ptrs, items, n_items, counters);
   else if (f64)
-    hipLaunchKernelGGL((persistent_kernel<double, false>), dim3(grid), dim3(256), 0, stream,
+    hipLaunchKernelGGL((persistent_kernel<double, false, 1>), dim3(grid), dim3(256), 0, stream,
                        table, ptrs, items, n_items, counters);
   else if (narrow)
-    hipLaunchKernelGGL((persistent_kernel<float, true>), dim3(grid), dim3(256), 0, stream,
+    hipLaunchKernelGGL((persistent_kernel<float, true, 4>), dim3(grid), dim3(256), 0, stream,
                        table, ptrs, items, n_items, counters);
   else
-    hipLaunchKernelGGL((persistent_kernel<float, false>), dim3(grid), dim3(256), 0, stream,
+    hipLaunchKernelGGL((persistent_kernel<float, false, 4>), dim3(grid), dim3(256), 0, stream,
                        table, ptrs, items, n_items, counters);
   return hipGetLastError();
 }
