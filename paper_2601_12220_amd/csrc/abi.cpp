@@ -699,9 +699,8 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
     B->plans.push_back(&p);
     GenEinsum &g = table[k];
     if (!g.narrow) B->narrow = false;
-    // Value reads per output: `rows` along the shared space (the row-dependent
-    // operands' exclusive sums at every shared row) and `once` for the other
-    // operands, which every lane of an output evaluates itself.
+    // Value reads per output: `per` at each shared row (the row-dependent
+    // operands' exclusive sums) and `once` for the other operands.
     double per = 0.0, once = 0.0;
     for (int op = 0; op < g.n_ops; ++op) {
       const double ex = (double)std::max<int64_t>(g.ex_size[op], 1);
@@ -709,21 +708,26 @@ int bes_batch_create(bes_ctx *ctx, bes_plan *const *plans, int32_t count, bes_ba
       else once += ex;
     }
     const int64_t sh = std::max<int64_t>(g.sh_size, 1);
-    const double rows = (double)sh * std::max(per, 1.0);
     // The einsum shares the machine with the others, so its decomposition is
     // the batch's own (a plan's tuned config fills the whole device alone):
     // lanes and chunks cut each work-item's serial chain of reads to about
-    // `chain`, lanes only while their redundant `once` reads stay below the
-    // useful ones, and a tile takes as many passes as fit in one chain.
+    // `chain`.  Lanes split the shared rows while each keeps at least half a
+    // chain and their share of the `once` sums stays below the row reads;
+    // where the `once` sums alone exceed a chain, lanes split them too
+    // (those reads cost more: each decodes its full index).  Chunks split
+    // the rows further while the rows exceed twice `chain`; a tile takes as
+    // many passes as fit in one chain.
+    const double rows = (double)sh * std::max(per, 1.0);
     int lanes = 1;
     while (lanes < 64 && lanes * 2 <= sh && rows / (lanes * 2) >= chain * 0.5 &&
            once * lanes * 2 <= rows)
       lanes *= 2;
+    while (lanes < 64 && once / lanes > chain) lanes *= 2;
     int chunks = 1;
     while (chunks < 64 && (int64_t)lanes * chunks * 2 <= sh &&
            rows / ((double)lanes * chunks) > 2.0 * chain)
       chunks *= 2;
-    const double lane_chain = once + rows / ((double)lanes * chunks);
+    const double lane_chain = once / lanes + rows / ((double)lanes * chunks);
     const int64_t per_pass = 256 / lanes;
     const int64_t passes =
         std::max<int64_t>(1, std::min<int64_t>((int64_t)(chain / lane_chain),
