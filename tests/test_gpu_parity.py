@@ -403,3 +403,39 @@ def test_generic_factored_and_split(ctx, dtype, split):
         torch.cuda.synchronize()
         for m in range(2):
             assert rel_fro(outs[m].double().cpu().numpy(), refs[m]) <= TOL[dtype], (split, m, rep)
+
+
+@pytest.mark.parametrize("nota", ["ank,qfi,n->i", "ij,ij->i"])
+@pytest.mark.parametrize("lanes", [1, 2, 8, 64])
+def test_generic_fp32_ill_conditioned_sum_any_lanes(ctx, nota, lanes):
+    """FP32 sums whose terms cancel to about 1/1000 of their absolute sum: the
+    generic template carries sums in FP64 and rounds the result once, so
+    every split of the sum across an output's lanes stays within a few FP32
+    roundings of the oracle (1e-6, far inside the 1e-5 bound that naive FP32
+    summation of such sums can miss).  In 'ank,qfi,n->i' the cancelling sum
+    belongs to the operand without shared indices (summed once per output,
+    dealt out across the lanes); in 'ij,ij->i' to the shared rows."""
+    import oracle
+    from paper_2601_12220_amd import make_operand
+    g = torch.Generator().manual_seed(1234)
+    if nota == "ank,qfi,n->i":
+        shapes = [(4, 8, 4), (32, 32, 8), (8,)]
+        x = torch.randn(32, 32, 8, generator=g, dtype=torch.float64)
+        arrs = [torch.randn(4, 8, 4, generator=g, dtype=torch.float64),
+                x - x.mean(dim=(0, 1), keepdim=True) + 1e-3,
+                torch.randn(8, generator=g, dtype=torch.float64)]
+    else:
+        shapes = [(16, 2048), (16, 2048)]
+        x = torch.randn(16, 2048, generator=g, dtype=torch.float64)
+        arrs = [x - x.mean(dim=1, keepdim=True) + 1e-3, torch.ones(16, 2048, dtype=torch.float64)]
+    arrs = [a.float().double() for a in arrs]         # FP32-exact inputs
+    names = [f"X{k}" for k in range(len(shapes))]
+    ops = {nm: (make_operand(s, "float32"), [nm]) for nm, s in zip(names, shapes)}
+    p = ctx.register(nota, [names], ops, arg_order=names)
+    p.set_config(capi.BES_T_GENERIC, 64, lanes, 1)
+    ref = oracle.einsum(nota, *[a.numpy() for a in arrs])
+    out = torch.full(ref.shape, float("nan"), dtype=torch.float32, device="cuda")
+    p.launch({nm: a.float().cuda() for nm, a in zip(names, arrs)}, [out])
+    torch.cuda.synchronize()
+    err = rel_fro(out.double().cpu().numpy(), ref)
+    assert err <= 1e-6, (nota, lanes, err)
