@@ -290,13 +290,29 @@ def bes_batch_create(ctx, plans):
     return h
 
 
-def _ptr_lists(src_lists, out_lists):
-    srcs = [_ptrs(s) for s in src_lists]
-    outs = [_ptrs(o) for o in out_lists]
+def _flat_lists(lists):
+    """One uint64 buffer holding every list back to back, and an array of
+    the lists' start addresses (the void *const *const * the C side reads).
+    Returns (array of starts as POINTER(POINTER(c_void_p)), keep-alive)."""
+    sizes = [max(1, len(l)) for l in lists]
+    buf = (ctypes.c_uint64 * max(1, sum(sizes)))()
+    base = ctypes.addressof(buf)
+    starts = []
+    off = 0
+    for l, n in zip(lists, sizes):
+        starts.append(base + 8 * off)
+        if l:
+            buf[off:off + len(l)] = [int(p) for p in l]
+        off += n
+    arr = (ctypes.c_uint64 * max(1, len(starts)))(*starts)
     PP = ctypes.POINTER(ctypes.c_void_p)
-    sarr = (PP * len(srcs))(*[ctypes.cast(s, PP) for s in srcs])
-    oarr = (PP * len(outs))(*[ctypes.cast(o, PP) for o in outs])
-    return sarr, oarr, (srcs, outs)
+    return ctypes.cast(arr, ctypes.POINTER(PP)), (buf, arr)
+
+
+def _ptr_lists(src_lists, out_lists):
+    sarr, ks = _flat_lists(src_lists)
+    oarr, ko = _flat_lists(out_lists)
+    return sarr, oarr, (ks, ko)
 
 
 def bes_batch_launch(h, src_lists, out_lists, stream: int = 0, _keep=None) -> None:
