@@ -265,7 +265,7 @@ def bes_ctx_stats(ctx):
 
 
 def _ptrs(ptrs):
-    return (ctypes.c_void_p * max(1, len(ptrs)))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+    return (ctypes.c_void_p * max(1, len(ptrs)))(*[int(p) for p in ptrs])
 
 
 def bes_plan_set_timing(h, start_event: int, stop_event: int) -> None:
